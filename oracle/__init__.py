@@ -1,0 +1,233 @@
+"""ORACLE — test infrastructure only.
+
+Plain CPU reference of the generalised geodesic distance transform computed by
+directional raster-scan passes (FastGeodis paper, section "Implementation"), plus
+the independent checkers that pin it (Dijkstra, the lambda = 0 closed form, path
+enumeration, per-pass chain brute force, reverse-mode gradient).  The arithmetic
+lives in ``ggdt_ref.c``; this module only marshals numpy arrays through ctypes.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library and
+never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ggdt_ref.c")
+_LIB = os.path.join(_HERE, "libggdt_ref.so")
+_CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+           "-shared", "-fPIC"]
+
+_lib = None
+
+
+def build() -> str:
+    """Compile ggdt_ref.c into libggdt_ref.so (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(shape):
+    return (ctypes.c_int * len(shape))(*shape)
+
+
+def _split(image, mask):
+    """image: (C, *spatial) or (*spatial) -> (C, spatial shape)."""
+    mask = np.asarray(mask)
+    spatial = mask.shape
+    image = np.asarray(image)
+    if image.shape == spatial:
+        image = image[None]
+    if image.shape[1:] != spatial or len(spatial) not in (2, 3):
+        raise ValueError(f"shape mismatch: image {image.shape} mask {spatial}")
+    return image, spatial
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with code {rc}")
+
+
+def passes_per_iteration(ndim: int) -> int:
+    return 2 * ndim
+
+
+def pass_schedule(ndim: int, iterations: int):
+    """(axis, sign) of every directional pass, in execution order."""
+    return [(a, s) for _ in range(iterations) for a in range(ndim) for s in (1, -1)]
+
+
+def ggdt(image, mask, spacing, v, lam, iterations, precision="f32", records=False):
+    """Fixed-iteration raster-scan GGDT.  Returns D (and records if asked:
+    uint8 array (passes, *spatial), 0 = keep, 1 + j = parent offset j)."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    C = image.shape[0]
+    nd = len(spatial)
+    npass = iterations * 2 * nd
+    rec = np.zeros((npass,) + spatial, dtype=np.uint8) if records else None
+    if precision == "f32":
+        img, m, sp = _f32(image), _f32(mask), _f32(spacing)
+        out = np.empty(spatial, dtype=np.float32)
+        fn, vv, ll = lib.ref_ggdt_f32, ctypes.c_float(v), ctypes.c_float(lam)
+    elif precision == "f64":
+        img, m, sp = _f64(image), _f64(mask), _f64(spacing)
+        out = np.empty(spatial, dtype=np.float64)
+        fn, vv, ll = lib.ref_ggdt_f64, ctypes.c_double(v), ctypes.c_double(lam)
+    else:
+        raise ValueError(precision)
+    rc = fn(nd, _dims(spatial), C, _p(img), _p(m), _p(sp), vv, ll, int(iterations), _p(out),
+            _p(rec) if rec is not None else None)
+    _check(rc, "ref_ggdt")
+    return (out, rec) if records else out
+
+
+def single_pass(image, D, spacing, lam, axis, sign, precision="f32", records=False):
+    """One directional pass applied to a copy of D."""
+    lib = _load()
+    image, spatial = _split(image, D)
+    C = image.shape[0]
+    rec = np.zeros(spatial, dtype=np.uint8) if records else None
+    if precision == "f32":
+        img, sp, out = _f32(image), _f32(spacing), _f32(D).copy()
+        rc = lib.ref_pass_f32(len(spatial), _dims(spatial), C, _p(img), _p(sp), ctypes.c_float(lam),
+                              int(axis), int(sign), _p(out), _p(rec) if rec is not None else None)
+    else:
+        img, sp, out = _f64(image), _f64(spacing), _f64(D).copy()
+        rc = lib.ref_pass_f64(len(spatial), _dims(spatial), C, _p(img), _p(sp), ctypes.c_double(lam),
+                              int(axis), int(sign), _p(out), _p(rec) if rec is not None else None)
+    _check(rc, "ref_pass")
+    return (out, rec) if records else out
+
+
+def until_converged(image, mask, spacing, v, lam, max_iterations=10000, precision="f32"):
+    """Iterate whole iterations until a fixed point; returns (D, iterations)."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    C = image.shape[0]
+    if precision == "f32":
+        img, m, sp = _f32(image), _f32(mask), _f32(spacing)
+        out = np.empty(spatial, dtype=np.float32)
+        n = lib.ref_ggdt_until_converged_f32(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp),
+                                             ctypes.c_float(v), ctypes.c_float(lam),
+                                             int(max_iterations), _p(out))
+    else:
+        img, m, sp = _f64(image), _f64(mask), _f64(spacing)
+        out = np.empty(spatial, dtype=np.float64)
+        n = lib.ref_ggdt_until_converged_f64(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp),
+                                             ctypes.c_double(v), ctypes.c_double(lam),
+                                             int(max_iterations), _p(out))
+    if n < 0:
+        raise RuntimeError(f"did not converge within {max_iterations} iterations (code {n})")
+    return out, n
+
+
+def dijkstra(image, mask, spacing, v, lam, precision="f64"):
+    """Multi-source Dijkstra on the 8/26-connected grid with the same edge cost."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    C = image.shape[0]
+    if precision == "f32":
+        img, m, sp = _f32(image), _f32(mask), _f32(spacing)
+        out = np.empty(spatial, dtype=np.float32)
+        rc = lib.ref_dijkstra_f32(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp),
+                                  ctypes.c_float(v), ctypes.c_float(lam), _p(out))
+    else:
+        img, m, sp = _f64(image), _f64(mask), _f64(spacing)
+        out = np.empty(spatial, dtype=np.float64)
+        rc = lib.ref_dijkstra_f64(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp),
+                                  ctypes.c_double(v), ctypes.c_double(lam), _p(out))
+    _check(rc, "ref_dijkstra")
+    return out
+
+
+def chamfer_closed_form(mask, spacing, v):
+    """lambda = 0 distances from the king-move chain formula, FP64, O(n^2)."""
+    lib = _load()
+    m = _f64(mask)
+    sp = _f64(spacing)
+    out = np.empty(m.shape, dtype=np.float64)
+    rc = lib.ref_chamfer_closed_form_f64(m.ndim, _dims(m.shape), _p(m), _p(sp), ctypes.c_double(v), _p(out))
+    _check(rc, "ref_chamfer_closed_form_f64")
+    return out
+
+
+def bruteforce_paths(image, mask, spacing, v, lam, prune=False, max_visits=2_000_000_000):
+    """Minimum over all simple paths (prune=False) or bound-pruned walks, FP64."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    img, m, sp = _f64(image), _f64(mask), _f64(spacing)
+    out = np.empty(spatial, dtype=np.float64)
+    lib.ref_bruteforce_paths_f64.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p]
+    rc = lib.ref_bruteforce_paths_f64(len(spatial), _dims(spatial), image.shape[0], _p(img), _p(m), _p(sp),
+                                      v, lam, int(bool(prune)), int(max_visits), _p(out))
+    _check(rc, "ref_bruteforce_paths_f64")
+    return out
+
+
+def pass_bruteforce(image, D_in, spacing, lam, axis, sign):
+    """One pass as a min over monotone chains, each target on its own, FP64."""
+    lib = _load()
+    image, spatial = _split(image, D_in)
+    img, sp, din = _f64(image), _f64(spacing), _f64(D_in)
+    out = np.empty(spatial, dtype=np.float64)
+    rc = lib.ref_pass_bruteforce_f64(len(spatial), _dims(spatial), image.shape[0], _p(img), _p(sp),
+                                     ctypes.c_double(lam), int(axis), int(sign), _p(din), _p(out))
+    _check(rc, "ref_pass_bruteforce_f64")
+    return out
+
+
+def backward(image, records, grad_out, spacing, v, lam, iterations, precision="f32"):
+    """Reverse-mode gradient of the fixed schedule; returns (dL/dI, dL/dM)."""
+    lib = _load()
+    g = np.asarray(grad_out)
+    image, spatial = _split(image, g)
+    C = image.shape[0]
+    rec = np.ascontiguousarray(records, dtype=np.uint8)
+    if rec.shape != (iterations * 2 * len(spatial),) + spatial:
+        raise ValueError(f"records shape {rec.shape}")
+    if precision == "f32":
+        img, sp, go = _f32(image), _f32(spacing), _f32(g)
+        gi = np.empty(image.shape, dtype=np.float32)
+        gm = np.empty(spatial, dtype=np.float32)
+        rc = lib.ref_ggdt_backward_f32(len(spatial), _dims(spatial), C, _p(img), _p(sp), ctypes.c_float(v),
+                                       ctypes.c_float(lam), int(iterations), _p(rec), _p(go), _p(gi), _p(gm))
+    else:
+        img, sp, go = _f64(image), _f64(spacing), _f64(g)
+        gi = np.empty(image.shape, dtype=np.float64)
+        gm = np.empty(spatial, dtype=np.float64)
+        rc = lib.ref_ggdt_backward_f64(len(spatial), _dims(spatial), C, _p(img), _p(sp), ctypes.c_double(v),
+                                       ctypes.c_double(lam), int(iterations), _p(rec), _p(go), _p(gi), _p(gm))
+    _check(rc, "ref_ggdt_backward")
+    return gi, gm

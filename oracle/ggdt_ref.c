@@ -1,0 +1,844 @@
+/*
+ * ORACLE — test infrastructure only.  Nothing on the product path may link,
+ * load or call this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or table with the
+ * HIP library.
+ *
+ * Plain, slow, single-threaded CPU reference of the generalised geodesic
+ * distance transform (GGDT) computed by directional raster-scan passes, as the
+ * FastGeodis paper describes it (section "Implementation": passes that update
+ * a whole row (2D) or plane (3D) in parallel from the previous row/plane; four
+ * passes in 2D, six in 3D).  The paper prints no formula; the one followed here
+ * is the generalised GDT of Criminisi et al. 2008 that the paper implements
+ * (section "Statement of need"):
+ *
+ *     D0(x) = v * M(x)
+ *     w(x,y) = sqrt((1 - lambda) * |x - y|_s^2 + lambda * sum_c (I_c(x) - I_c(y))^2)
+ *     one pass: D(x) <- min(D(x), min over y in the previous row/plane of D(y) + w(x,y))
+ *
+ * Readings of points the paper leaves open (each listed in the design doc):
+ *  - only the 3 (2D) / 9 (3D) neighbours in the previous row/plane are used;
+ *    the current value D(x) takes part in the min ("keep");
+ *  - passes per iteration: for axis 0..ndim-1: ascending, then descending;
+ *  - neighbours outside the grid are skipped; the first row/plane of a pass is
+ *    left unchanged;
+ *  - spacing is given in array-axis order;
+ *  - the channel term is the plain sum of squared differences, channel order 0..C-1;
+ *  - ties keep the earlier candidate (strict <), candidates in lexicographic
+ *    order of the offset over the non-scan axes (ascending axis), each -1, 0, +1.
+ *
+ * FP32 operation sequence (one rounding per line):
+ *     d_c  = I_c(x) - I_c(y)
+ *     g    = d_0 * d_0;  g = fmaf(d_c, d_c, g) for c = 1..C-1
+ *     q    = fmaf(lambda, g, A)      A = (float)((1 - (double)lambda) * S),
+ *                                    S = sum over axes b ascending of (s_b * |dx_b|)^2 in double
+ *     w    = sqrtf(q)
+ *     cand = D(y) + w
+ * The FP64 variant is the same sequence in double with A = (1 - lambda) * S unrounded.
+ *
+ * Besides the schedule this file holds independent checkers used to pin it:
+ * multi-source Dijkstra, the lambda = 0 closed form, exhaustive and
+ * bound-pruned path enumeration, a per-pass chain brute force and the exact
+ * reverse-mode gradient of the schedule.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define REF_OK 0
+#define REF_EINVAL -1
+#define REF_ENOMEM -2
+
+/* ------------------------------------------------------------------ grid */
+
+typedef struct {
+  int ndim;
+  int dims[3];
+  long strides[3];
+  long n;
+} grid_t;
+
+static int grid_init(grid_t* g, int ndim, const int* dims) {
+  if (ndim != 2 && ndim != 3) return REF_EINVAL;
+  g->ndim = ndim;
+  long n = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (dims[i] < 1) return REF_EINVAL;
+    g->dims[i] = dims[i];
+    n *= dims[i];
+  }
+  long s = 1;
+  for (int i = ndim - 1; i >= 0; --i) {
+    g->strides[i] = s;
+    s *= dims[i];
+  }
+  g->n = n;
+  return REF_OK;
+}
+
+static void unflatten(const grid_t* g, long idx, int* c) {
+  for (int i = 0; i < g->ndim; ++i) {
+    c[i] = (int)(idx / g->strides[i]);
+    idx -= (long)c[i] * g->strides[i];
+  }
+}
+
+static long flatten(const grid_t* g, const int* c) {
+  long idx = 0;
+  for (int i = 0; i < g->ndim; ++i) idx += (long)c[i] * g->strides[i];
+  return idx;
+}
+
+static int in_grid(const grid_t* g, const int* c) {
+  for (int i = 0; i < g->ndim; ++i)
+    if (c[i] < 0 || c[i] >= g->dims[i]) return 0;
+  return 1;
+}
+
+
+/* Iterator over every voxel of the plane x_a = k, other axes in row-major order. */
+typedef struct {
+  const grid_t* g;
+  int a, o[2], no;
+  int xc[3];
+  int done;
+} plane_it;
+
+static void plane_first(plane_it* it, const grid_t* g, int a, int k) {
+  it->g = g;
+  it->a = a;
+  it->no = 0;
+  for (int b = 0; b < g->ndim; ++b)
+    if (b != a) it->o[it->no++] = b;
+  it->xc[0] = it->xc[1] = it->xc[2] = 0;
+  it->xc[a] = k;
+  it->done = 0;
+}
+
+static void plane_next(plane_it* it) {
+  for (int i = it->no - 1; i >= 0; --i) {
+    int b = it->o[i];
+    if (++it->xc[b] < it->g->dims[b]) return;
+    it->xc[b] = 0;
+  }
+  it->done = 1;
+}
+
+/* S = sum over axes b (ascending) of (s_b * |dx_b|)^2, in double. */
+static double spatial_sq(int ndim, const double* spacing, const int* dx) {
+  double S = 0.0;
+  for (int b = 0; b < ndim; ++b) {
+    double t = spacing[b] * (double)abs(dx[b]);
+    S = S + t * t;
+  }
+  return S;
+}
+
+/* Offsets of a pass along axis a: displacement from the updated voxel x back to
+ * its candidate parent y is -sign on axis a and delta_b in {-1,0,+1} on every
+ * other axis.  Enumerated lexicographically over the non-scan axes (ascending
+ * axis index, each component -1, 0, +1).  Returns the count, 3^(ndim-1). */
+static int pass_offsets(int ndim, int a, int (*delta)[3]) {
+  int other[2], no = 0;
+  for (int b = 0; b < ndim; ++b)
+    if (b != a) other[no++] = b;
+  int count = 1;
+  for (int i = 0; i < no; ++i) count *= 3;
+  for (int j = 0; j < count; ++j) {
+    int rem = j;
+    delta[j][0] = delta[j][1] = delta[j][2] = 0;
+    for (int i = no - 1; i >= 0; --i) {
+      delta[j][other[i]] = rem % 3 - 1;
+      rem /= 3;
+    }
+  }
+  return count;
+}
+
+/* ----------------------------------------------------- edge cost, FP32 / FP64 */
+
+static float edge_w_f32(const float* img, long cs, int C, long x, long y, float lam, float A) {
+  float d = img[x] - img[y];
+  float g = d * d;
+  for (int c = 1; c < C; ++c) {
+    float dc = img[(long)c * cs + x] - img[(long)c * cs + y];
+    g = fmaf(dc, dc, g);
+  }
+  float q = fmaf(lam, g, A);
+  return sqrtf(q);
+}
+
+static double edge_w_f64(const double* img, long cs, int C, long x, long y, double lam, double A) {
+  double d = img[x] - img[y];
+  double g = d * d;
+  for (int c = 1; c < C; ++c) {
+    double dc = img[(long)c * cs + x] - img[(long)c * cs + y];
+    g = fma(dc, dc, g);
+  }
+  double q = fma(lam, g, A);
+  return sqrt(q);
+}
+
+static int check_common(int ndim, const int* dims, int C, const void* image, const void* mask,
+                        const void* spacing, int iterations, const void* out, grid_t* g) {
+  if (!dims || !image || !mask || !spacing || !out) return REF_EINVAL;
+  if (C < 1 || iterations < 0) return REF_EINVAL;
+  return grid_init(g, ndim, dims);
+}
+
+/* ------------------------------------------------------------ the schedule */
+
+/* One directional pass along axis a in direction sign (+1 / -1), in place on D.
+ * rec (nullable) receives one byte per voxel: 0 = keep, 1 + j = parent through
+ * offset j of pass_offsets(). */
+static void pass_f32(const grid_t* g, int C, const float* img, const double* sp, float lam,
+                     int a, int sign, float* D, uint8_t* rec) {
+  int delta[9][3];
+  int nd = pass_offsets(g->ndim, a, delta);
+  float A[9];
+  for (int j = 0; j < nd; ++j) {
+    int dx[3] = {delta[j][0], delta[j][1], delta[j][2]};
+    dx[a] = 1;
+    A[j] = (float)((1.0 - (double)lam) * spatial_sq(g->ndim, sp, dx));
+  }
+  int Na = g->dims[a];
+  long cs = g->n;
+  if (rec) {
+    /* the first plane in scan order is never modified */
+    plane_it pf;
+    for (plane_first(&pf, g, a, sign > 0 ? 0 : Na - 1); !pf.done; plane_next(&pf))
+      rec[flatten(g, pf.xc)] = 0;
+  }
+  for (int t = 1; t < Na; ++t) {
+    int k = sign > 0 ? t : Na - 1 - t;
+    /* all voxels of plane k; they read plane k - sign only */
+    plane_it pi;
+    for (plane_first(&pi, g, a, k); !pi.done; plane_next(&pi)) {
+      const int* xc = pi.xc;
+      long i = flatten(g, xc);
+      float best = D[i];
+      uint8_t choice = 0;
+      for (int j = 0; j < nd; ++j) {
+        int yc[3];
+        for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + delta[j][b];
+        yc[a] = k - sign;
+        if (!in_grid(g, yc)) continue;
+        long y = flatten(g, yc);
+        float w = edge_w_f32(img, cs, C, i, y, lam, A[j]);
+        float cand = D[y] + w;
+        if (cand < best) {
+          best = cand;
+          choice = (uint8_t)(1 + j);
+        }
+      }
+      D[i] = best;
+      if (rec) rec[i] = choice;
+    }
+  }
+}
+
+static void pass_f64(const grid_t* g, int C, const double* img, const double* sp, double lam,
+                     int a, int sign, double* D, uint8_t* rec) {
+  int delta[9][3];
+  int nd = pass_offsets(g->ndim, a, delta);
+  double A[9];
+  for (int j = 0; j < nd; ++j) {
+    int dx[3] = {delta[j][0], delta[j][1], delta[j][2]};
+    dx[a] = 1;
+    A[j] = (1.0 - lam) * spatial_sq(g->ndim, sp, dx);
+  }
+  int Na = g->dims[a];
+  long cs = g->n;
+  if (rec) {
+    plane_it pf;
+    for (plane_first(&pf, g, a, sign > 0 ? 0 : Na - 1); !pf.done; plane_next(&pf))
+      rec[flatten(g, pf.xc)] = 0;
+  }
+  for (int t = 1; t < Na; ++t) {
+    int k = sign > 0 ? t : Na - 1 - t;
+    plane_it pi;
+    for (plane_first(&pi, g, a, k); !pi.done; plane_next(&pi)) {
+      const int* xc = pi.xc;
+      long i = flatten(g, xc);
+      double best = D[i];
+      uint8_t choice = 0;
+      for (int j = 0; j < nd; ++j) {
+        int yc[3];
+        for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + delta[j][b];
+        yc[a] = k - sign;
+        if (!in_grid(g, yc)) continue;
+        long y = flatten(g, yc);
+        double w = edge_w_f64(img, cs, C, i, y, lam, A[j]);
+        double cand = D[y] + w;
+        if (cand < best) {
+          best = cand;
+          choice = (uint8_t)(1 + j);
+        }
+      }
+      D[i] = best;
+      if (rec) rec[i] = choice;
+    }
+  }
+}
+
+/* Number of directional passes in one iteration. */
+int ref_passes_per_iteration(int ndim) { return 2 * ndim; }
+
+/* Full fixed-iteration schedule, FP32.  image: (C, dims...) channel-planar;
+ * mask: (dims...); spacing: ndim values in array-axis order; out: (dims...).
+ * records (nullable): iterations * 2*ndim planes of n bytes, pass-major. */
+int ref_ggdt_f32(int ndim, const int* dims, int C, const float* image, const float* mask,
+                 const float* spacing, float v, float lam, int iterations, float* out,
+                 uint8_t* records) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (rc) return rc;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  int p = 0;
+  for (int it = 0; it < iterations; ++it)
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s, ++p)
+        pass_f32(&g, C, image, sp, lam, a, s == 0 ? +1 : -1, out, records ? records + (long)p * g.n : NULL);
+  return REF_OK;
+}
+
+int ref_ggdt_f64(int ndim, const int* dims, int C, const double* image, const double* mask,
+                 const double* spacing, double v, double lam, int iterations, double* out,
+                 uint8_t* records) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (rc) return rc;
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  int p = 0;
+  for (int it = 0; it < iterations; ++it)
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s, ++p)
+        pass_f64(&g, C, image, spacing, lam, a, s == 0 ? +1 : -1, out, records ? records + (long)p * g.n : NULL);
+  return REF_OK;
+}
+
+/* A single directional pass applied to a given D (in place), FP32 / FP64.
+ * Lets a caller compose the schedule pass by pass. */
+int ref_pass_f32(int ndim, const int* dims, int C, const float* image, const float* spacing,
+                 float lam, int axis, int sign, float* D, uint8_t* rec) {
+  grid_t g;
+  if (!dims || !image || !spacing || !D || C < 1) return REF_EINVAL;
+  if (grid_init(&g, ndim, dims)) return REF_EINVAL;
+  if (axis < 0 || axis >= ndim || (sign != 1 && sign != -1)) return REF_EINVAL;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  pass_f32(&g, C, image, sp, lam, axis, sign, D, rec);
+  return REF_OK;
+}
+
+int ref_pass_f64(int ndim, const int* dims, int C, const double* image, const double* spacing,
+                 double lam, int axis, int sign, double* D, uint8_t* rec) {
+  grid_t g;
+  if (!dims || !image || !spacing || !D || C < 1) return REF_EINVAL;
+  if (grid_init(&g, ndim, dims)) return REF_EINVAL;
+  if (axis < 0 || axis >= ndim || (sign != 1 && sign != -1)) return REF_EINVAL;
+  pass_f64(&g, C, image, spacing, lam, axis, sign, D, rec);
+  return REF_OK;
+}
+
+/* Iterate whole iterations until one changes no voxel bitwise (at most
+ * max_iterations).  Returns the number of iterations after which the state was
+ * already fixed, or -1 if the cap was hit; out holds the final state. */
+int ref_ggdt_until_converged_f32(int ndim, const int* dims, int C, const float* image,
+                                 const float* mask, const float* spacing, float v, float lam,
+                                 int max_iterations, float* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, max_iterations, out, &g);
+  if (rc) return rc;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  float* prev = (float*)malloc(sizeof(float) * g.n);
+  if (!prev) return REF_ENOMEM;
+  int result = -1;
+  for (int it = 1; it <= max_iterations; ++it) {
+    memcpy(prev, out, sizeof(float) * g.n);
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s) pass_f32(&g, C, image, sp, lam, a, s == 0 ? +1 : -1, out, NULL);
+    if (memcmp(prev, out, sizeof(float) * g.n) == 0) {
+      result = it - 1;
+      break;
+    }
+  }
+  free(prev);
+  return result;
+}
+
+int ref_ggdt_until_converged_f64(int ndim, const int* dims, int C, const double* image,
+                                 const double* mask, const double* spacing, double v, double lam,
+                                 int max_iterations, double* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, max_iterations, out, &g);
+  if (rc) return rc;
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  double* prev = (double*)malloc(sizeof(double) * g.n);
+  if (!prev) return REF_ENOMEM;
+  int result = -1;
+  for (int it = 1; it <= max_iterations; ++it) {
+    memcpy(prev, out, sizeof(double) * g.n);
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s) pass_f64(&g, C, image, spacing, lam, a, s == 0 ? +1 : -1, out, NULL);
+    if (memcmp(prev, out, sizeof(double) * g.n) == 0) {
+      result = it - 1;
+      break;
+    }
+  }
+  free(prev);
+  return result;
+}
+
+/* ------------------------------------------------------ multi-source Dijkstra */
+
+typedef struct {
+  double key;
+  long node;
+} heap_item;
+
+typedef struct {
+  heap_item* a;
+  long size, cap;
+} heap_t;
+
+static int heap_push(heap_t* h, double key, long node) {
+  if (h->size == h->cap) {
+    long nc = h->cap ? 2 * h->cap : 1024;
+    heap_item* na = (heap_item*)realloc(h->a, sizeof(heap_item) * nc);
+    if (!na) return REF_ENOMEM;
+    h->a = na;
+    h->cap = nc;
+  }
+  long i = h->size++;
+  h->a[i].key = key;
+  h->a[i].node = node;
+  while (i > 0) {
+    long p = (i - 1) / 2;
+    if (h->a[p].key <= h->a[i].key) break;
+    heap_item t = h->a[p];
+    h->a[p] = h->a[i];
+    h->a[i] = t;
+    i = p;
+  }
+  return REF_OK;
+}
+
+static heap_item heap_pop(heap_t* h) {
+  heap_item top = h->a[0];
+  h->a[0] = h->a[--h->size];
+  long i = 0;
+  for (;;) {
+    long l = 2 * i + 1, r = l + 1, m = i;
+    if (l < h->size && h->a[l].key < h->a[m].key) m = l;
+    if (r < h->size && h->a[r].key < h->a[m].key) m = r;
+    if (m == i) break;
+    heap_item t = h->a[m];
+    h->a[m] = h->a[i];
+    h->a[i] = t;
+    i = m;
+  }
+  return top;
+}
+
+/* Shortest paths on the 8- (2D) / 26- (3D) connected grid, every voxel a source
+ * with initial cost v*M.  Edge cost is the same w as the scan uses (w is
+ * symmetric); path costs are accumulated from the source towards the target,
+ * one rounding per edge, in the working precision. */
+int ref_dijkstra_f32(int ndim, const int* dims, int C, const float* image, const float* mask,
+                     const float* spacing, float v, float lam, float* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, 0, out, &g);
+  if (rc) return rc;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  int nb = 0, off[26][3];
+  float A[26];
+  for (int dz = (ndim == 3 ? -1 : 0); dz <= (ndim == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int d[3];
+        if (ndim == 3) { d[0] = dz; d[1] = dy; d[2] = dx; }
+        else { d[0] = dy; d[1] = dx; d[2] = 0; }
+        if (d[0] == 0 && d[1] == 0 && d[2] == 0) continue;
+        memcpy(off[nb], d, sizeof d);
+        A[nb] = (float)((1.0 - (double)lam) * spatial_sq(ndim, sp, d));
+        ++nb;
+      }
+  char* done = (char*)calloc(g.n, 1);
+  heap_t h = {0, 0, 0};
+  if (!done) return REF_ENOMEM;
+  for (long i = 0; i < g.n; ++i) {
+    out[i] = v * mask[i];
+    if (heap_push(&h, (double)out[i], i)) { free(done); free(h.a); return REF_ENOMEM; }
+  }
+  while (h.size > 0) {
+    heap_item it = heap_pop(&h);
+    long u = it.node;
+    if (done[u] || it.key != (double)out[u]) continue;
+    done[u] = 1;
+    int uc[3];
+    unflatten(&g, u, uc);
+    for (int j = 0; j < nb; ++j) {
+      int zc[3];
+      for (int b = 0; b < ndim; ++b) zc[b] = uc[b] + off[j][b];
+      if (!in_grid(&g, zc)) continue;
+      long z = flatten(&g, zc);
+      if (done[z]) continue;
+      float w = edge_w_f32(image, g.n, C, z, u, lam, A[j]);
+      float cand = out[u] + w;
+      if (cand < out[z]) {
+        out[z] = cand;
+        if (heap_push(&h, (double)cand, z)) { free(done); free(h.a); return REF_ENOMEM; }
+      }
+    }
+  }
+  free(done);
+  free(h.a);
+  return REF_OK;
+}
+
+int ref_dijkstra_f64(int ndim, const int* dims, int C, const double* image, const double* mask,
+                     const double* spacing, double v, double lam, double* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, 0, out, &g);
+  if (rc) return rc;
+  int nb = 0, off[26][3];
+  double A[26];
+  for (int dz = (ndim == 3 ? -1 : 0); dz <= (ndim == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int d[3];
+        if (ndim == 3) { d[0] = dz; d[1] = dy; d[2] = dx; }
+        else { d[0] = dy; d[1] = dx; d[2] = 0; }
+        if (d[0] == 0 && d[1] == 0 && d[2] == 0) continue;
+        memcpy(off[nb], d, sizeof d);
+        A[nb] = (1.0 - lam) * spatial_sq(ndim, spacing, d);
+        ++nb;
+      }
+  char* done = (char*)calloc(g.n, 1);
+  heap_t h = {0, 0, 0};
+  if (!done) return REF_ENOMEM;
+  for (long i = 0; i < g.n; ++i) {
+    out[i] = v * mask[i];
+    if (heap_push(&h, out[i], i)) { free(done); free(h.a); return REF_ENOMEM; }
+  }
+  while (h.size > 0) {
+    heap_item it = heap_pop(&h);
+    long u = it.node;
+    if (done[u] || it.key != out[u]) continue;
+    done[u] = 1;
+    int uc[3];
+    unflatten(&g, u, uc);
+    for (int j = 0; j < nb; ++j) {
+      int zc[3];
+      for (int b = 0; b < ndim; ++b) zc[b] = uc[b] + off[j][b];
+      if (!in_grid(&g, zc)) continue;
+      long z = flatten(&g, zc);
+      if (done[z]) continue;
+      double w = edge_w_f64(image, g.n, C, z, u, lam, A[j]);
+      double cand = out[u] + w;
+      if (cand < out[z]) {
+        out[z] = cand;
+        if (heap_push(&h, cand, z)) { free(done); free(h.a); return REF_ENOMEM; }
+      }
+    }
+  }
+  free(done);
+  free(h.a);
+  return REF_OK;
+}
+
+/* ------------------------------------------------- lambda = 0 closed form */
+
+/* With lambda = 0 the edge cost is the spacing-weighted length of a king move.
+ * The cheapest king-move path for a displacement with per-axis step counts
+ * sorted n1 >= n2 >= n3 (axes i1, i2, i3) uses n3 moves along all three axes,
+ * n2 - n3 along {i1, i2} and n1 - n2 along i1 alone.  out(x) = min over every
+ * voxel y of v*M(y) + that chain length, in FP64 (O(n^2); small grids only). */
+int ref_chamfer_closed_form_f64(int ndim, const int* dims, const double* mask,
+                                const double* spacing, double v, double* out) {
+  grid_t g;
+  if (!dims || !mask || !spacing || !out) return REF_EINVAL;
+  if (grid_init(&g, ndim, dims)) return REF_EINVAL;
+  for (long x = 0; x < g.n; ++x) {
+    int xc[3];
+    unflatten(&g, x, xc);
+    double best = v * mask[x];
+    for (long y = 0; y < g.n; ++y) {
+      int yc[3];
+      unflatten(&g, y, yc);
+      int cnt[3] = {0, 0, 0}, ax[3] = {0, 1, 2};
+      for (int b = 0; b < ndim; ++b) cnt[b] = abs(xc[b] - yc[b]);
+      /* sort axes by count, descending */
+      for (int i = 0; i < ndim; ++i)
+        for (int j = i + 1; j < ndim; ++j)
+          if (cnt[ax[j]] > cnt[ax[i]]) { int t = ax[i]; ax[i] = ax[j]; ax[j] = t; }
+      double s1 = spacing[ax[0]] * spacing[ax[0]];
+      double s2 = ndim > 1 ? spacing[ax[1]] * spacing[ax[1]] : 0.0;
+      double s3 = ndim > 2 ? spacing[ax[2]] * spacing[ax[2]] : 0.0;
+      double n1 = cnt[ax[0]], n2 = ndim > 1 ? cnt[ax[1]] : 0, n3 = ndim > 2 ? cnt[ax[2]] : 0;
+      double len = n3 * sqrt(s1 + s2 + s3) + (n2 - n3) * sqrt(s1 + s2) + (n1 - n2) * sqrt(s1);
+      double c = v * mask[y] + len;
+      if (c < best) best = c;
+    }
+    out[x] = best;
+  }
+  return REF_OK;
+}
+
+/* ---------------------------------------------------- path enumeration */
+
+typedef struct {
+  const grid_t* g;
+  int C;
+  const double* img;
+  const double* sp;
+  double lam;
+  double* best;
+  char* on_path;
+  long visits;
+  long max_visits;
+  int prune;
+} dfs_ctx;
+
+static double edge_between_f64(const dfs_ctx* c, long x, long y) {
+  int xc[3], yc[3], d[3] = {0, 0, 0};
+  unflatten(c->g, x, xc);
+  unflatten(c->g, y, yc);
+  for (int b = 0; b < c->g->ndim; ++b) d[b] = xc[b] - yc[b];
+  double A = (1.0 - c->lam) * spatial_sq(c->g->ndim, c->sp, d);
+  return edge_w_f64(c->img, c->g->n, c->C, x, y, c->lam, A);
+}
+
+/* Extend a path that currently ends at u with accumulated cost `cost` (folded
+ * from the path's start).  Without pruning every simple path is visited; with
+ * pruning a branch stops once its cost is no better than the best known cost
+ * of its end voxel (exact for non-negative edges and monotone rounding). */
+static int dfs(dfs_ctx* c, long u, double cost) {
+  if (++c->visits > c->max_visits) return -1;
+  if (cost < c->best[u]) c->best[u] = cost;
+  int uc[3];
+  unflatten(c->g, u, uc);
+  int nd = c->g->ndim;
+  for (int dz = (nd == 3 ? -1 : 0); dz <= (nd == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int d[3];
+        if (nd == 3) { d[0] = dz; d[1] = dy; d[2] = dx; }
+        else { d[0] = dy; d[1] = dx; d[2] = 0; }
+        if (!d[0] && !d[1] && !d[2]) continue;
+        int zc[3];
+        for (int b = 0; b < nd; ++b) zc[b] = uc[b] + d[b];
+        if (!in_grid(c->g, zc)) continue;
+        long z = flatten(c->g, zc);
+        if (c->on_path[z]) continue;
+        double nc = cost + edge_between_f64(c, z, u);
+        if (c->prune && nc >= c->best[z]) continue;
+        c->on_path[z] = 1;
+        int r = dfs(c, z, nc);
+        c->on_path[z] = 0;
+        if (r) return r;
+      }
+  return 0;
+}
+
+/* Minimum over all simple paths (prune = 0) or over all walks with
+ * bound pruning (prune = 1), every voxel a start with cost v*M.  Returns -1 if
+ * max_visits was exceeded. */
+int ref_bruteforce_paths_f64(int ndim, const int* dims, int C, const double* image,
+                             const double* mask, const double* spacing, double v, double lam,
+                             int prune, long max_visits, double* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, 0, out, &g);
+  if (rc) return rc;
+  dfs_ctx c;
+  c.g = &g; c.C = C; c.img = image; c.sp = spacing; c.lam = lam;
+  c.best = out; c.visits = 0; c.max_visits = max_visits; c.prune = prune;
+  c.on_path = (char*)calloc(g.n, 1);
+  if (!c.on_path) return REF_ENOMEM;
+  for (long i = 0; i < g.n; ++i) out[i] = INFINITY;
+  int r = 0;
+  for (long s = 0; s < g.n && !r; ++s) {
+    double start = v * mask[s];
+    if (prune && start >= out[s] && out[s] != INFINITY) continue;
+    c.on_path[s] = 1;
+    r = dfs(&c, s, start);
+    c.on_path[s] = 0;
+  }
+  free(c.on_path);
+  return r ? -1 : REF_OK;
+}
+
+/* One pass as a minimum over chains: for a target x in plane k (scan order),
+ * every chain y_j -> ... -> x that visits one plane per step (planes j..k, with
+ * offsets -1/0/+1 on the other axes) contributes D_in(y_j) folded with its edge
+ * costs; D_out(x) = min(D_in(x), all such chains).  No sweeping: each target is
+ * evaluated on its own from D_in only. */
+typedef struct {
+  const grid_t* g;
+  int C, a, sign;
+  const double* img;
+  const double* sp;
+  double lam;
+  const double* Din;
+  long chain[512];
+} chain_ctx;
+
+static void chain_eval(chain_ctx* c, int len, double* best) {
+  /* chain[len-1] is the start (furthest back), chain[0] the target */
+  double cost = c->Din[c->chain[len - 1]];
+  for (int i = len - 1; i > 0; --i) {
+    long y = c->chain[i], x = c->chain[i - 1];
+    int xc[3], yc[3], d[3] = {0, 0, 0};
+    unflatten(c->g, x, xc);
+    unflatten(c->g, y, yc);
+    for (int b = 0; b < c->g->ndim; ++b) d[b] = xc[b] - yc[b];
+    double A = (1.0 - c->lam) * spatial_sq(c->g->ndim, c->sp, d);
+    cost = cost + edge_w_f64(c->img, c->g->n, c->C, x, y, c->lam, A);
+  }
+  if (cost < *best) *best = cost;
+}
+
+static void chain_rec(chain_ctx* c, int len, double* best) {
+  /* every chain of length >= 2 ending at chain[0] is a candidate */
+  if (len >= 2) chain_eval(c, len, best);
+  long u = c->chain[len - 1];
+  int uc[3];
+  unflatten(c->g, u, uc);
+  int Na = c->g->dims[c->a];
+  int prev = uc[c->a] - c->sign;
+  if (prev < 0 || prev >= Na) return;
+  int delta[9][3];
+  int nd = pass_offsets(c->g->ndim, c->a, delta);
+  for (int j = 0; j < nd; ++j) {
+    int yc[3];
+    for (int b = 0; b < c->g->ndim; ++b) yc[b] = uc[b] + delta[j][b];
+    yc[c->a] = prev;
+    if (!in_grid(c->g, yc)) continue;
+    c->chain[len] = flatten(c->g, yc);
+    chain_rec(c, len + 1, best);
+  }
+}
+
+int ref_pass_bruteforce_f64(int ndim, const int* dims, int C, const double* image,
+                            const double* spacing, double lam, int axis, int sign,
+                            const double* D_in, double* D_out) {
+  grid_t g;
+  if (!dims || !image || !spacing || !D_in || !D_out || C < 1) return REF_EINVAL;
+  if (grid_init(&g, ndim, dims)) return REF_EINVAL;
+  if (axis < 0 || axis >= ndim || (sign != 1 && sign != -1)) return REF_EINVAL;
+  if (g.dims[axis] > 500) return REF_EINVAL;
+  chain_ctx c;
+  c.g = &g; c.C = C; c.a = axis; c.sign = sign; c.img = image; c.sp = spacing; c.lam = lam;
+  c.Din = D_in;
+  for (long x = 0; x < g.n; ++x) {
+    double best = D_in[x];
+    c.chain[0] = x;
+    chain_rec(&c, 1, &best);
+    D_out[x] = best;
+  }
+  return REF_OK;
+}
+
+/* ------------------------------------------------ reverse-mode gradient */
+
+/* Exact reverse of the fixed schedule given its records (one byte per voxel
+ * per pass, as written by ref_ggdt_*).  L is any loss with dL/dD = grad_out.
+ * Walks passes in reverse and, inside a pass, planes against the scan order.
+ * For plane k (the target plane) and its predecessor plane kp:
+ *   - every y in plane kp gathers, over offsets j in canonical order, from the
+ *     child x = y - delta_j in plane k whose record is 1 + j:
+ *         abar(y) += abar(x);  Ibar_c(y) -= coef * d_c
+ *   - then every updated x in plane k (record != 0):
+ *         Ibar_c(x) += coef * d_c;  abar(x) = 0
+ * with d_c = I_c(x) - I_c(y), coef = (abar(x) * lambda) / w (0 when w = 0).
+ * Finally dL/dM = v * abar and dL/dI = Ibar. */
+#define DEFINE_BACKWARD(NAME, T, EDGE, CASTSP)                                                   \
+  int NAME(int ndim, const int* dims, int C, const T* image, const T* spacing_in, T v, T lam,     \
+           int iterations, const uint8_t* records, const T* grad_out, T* grad_image,             \
+           T* grad_mask) {                                                                       \
+    grid_t g;                                                                                    \
+    if (!dims || !image || !spacing_in || !records || !grad_out || !grad_image || !grad_mask)    \
+      return REF_EINVAL;                                                                         \
+    if (C < 1 || iterations < 0 || grid_init(&g, ndim, dims)) return REF_EINVAL;                 \
+    double sp[3];                                                                                \
+    for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing_in[b];                                \
+    T* abar = grad_mask;                                                                         \
+    for (long i = 0; i < g.n; ++i) abar[i] = grad_out[i];                                        \
+    for (long i = 0; i < (long)C * g.n; ++i) grad_image[i] = (T)0;                               \
+    int npass = 2 * ndim;                                                                        \
+    for (int p = iterations * npass - 1; p >= 0; --p) {                                          \
+      int a = (p % npass) / 2, sign = (p % 2 == 0) ? 1 : -1;                                     \
+      const uint8_t* rec = records + (long)p * g.n;                                              \
+      int delta[9][3];                                                                           \
+      int nd = pass_offsets(ndim, a, delta);                                                     \
+      T A[9];                                                                                    \
+      for (int j = 0; j < nd; ++j) {                                                             \
+        int dx[3] = {delta[j][0], delta[j][1], delta[j][2]};                                     \
+        dx[a] = 1;                                                                               \
+        A[j] = CASTSP((1.0 - (double)lam) * spatial_sq(ndim, sp, dx));                           \
+      }                                                                                          \
+      int Na = g.dims[a];                                                                        \
+      for (int t = Na - 1; t >= 1; --t) {                                                        \
+        int k = sign > 0 ? t : Na - 1 - t;                                                       \
+        int kp = k - sign;                                                                       \
+        plane_it py;                                                                             \
+        for (plane_first(&py, &g, a, kp); !py.done; plane_next(&py)) {                           \
+          const int* yc = py.xc;                                                                 \
+          long y = flatten(&g, yc);                                                              \
+          for (int j = 0; j < nd; ++j) {                                                         \
+            int xc[3];                                                                           \
+            for (int b = 0; b < ndim; ++b) xc[b] = yc[b] - delta[j][b];                          \
+            xc[a] = k;                                                                           \
+            if (!in_grid(&g, xc)) continue;                                                      \
+            long x = flatten(&g, xc);                                                            \
+            if (rec[x] != 1 + j) continue;                                                       \
+            abar[y] = abar[y] + abar[x];                                                         \
+            T w = EDGE(image, g.n, C, x, y, lam, A[j]);                                          \
+            if (w > (T)0) {                                                                      \
+              T coef = (abar[x] * lam) / w;                                                      \
+              for (int c = 0; c < C; ++c) {                                                      \
+                T d = image[(long)c * g.n + x] - image[(long)c * g.n + y];                       \
+                grad_image[(long)c * g.n + y] = grad_image[(long)c * g.n + y] - coef * d;        \
+              }                                                                                  \
+            }                                                                                    \
+          }                                                                                      \
+        }                                                                                        \
+        plane_it px;                                                                             \
+        for (plane_first(&px, &g, a, k); !px.done; plane_next(&px)) {                            \
+          const int* xc = px.xc;                                                                 \
+          long x = flatten(&g, xc);                                                              \
+          if (rec[x] == 0) continue;                                                             \
+          int j = rec[x] - 1;                                                                    \
+          int yc[3];                                                                             \
+          for (int b = 0; b < ndim; ++b) yc[b] = xc[b] + delta[j][b];                            \
+          yc[a] = kp;                                                                            \
+          long y = flatten(&g, yc);                                                              \
+          T w = EDGE(image, g.n, C, x, y, lam, A[j]);                                            \
+          if (w > (T)0) {                                                                        \
+            T coef = (abar[x] * lam) / w;                                                        \
+            for (int c = 0; c < C; ++c) {                                                        \
+              T d = image[(long)c * g.n + x] - image[(long)c * g.n + y];                         \
+              grad_image[(long)c * g.n + x] = grad_image[(long)c * g.n + x] + coef * d;          \
+            }                                                                                    \
+          }                                                                                      \
+          abar[x] = (T)0;                                                                        \
+        }                                                                                        \
+      }                                                                                          \
+    }                                                                                            \
+    for (long i = 0; i < g.n; ++i) grad_mask[i] = v * abar[i];                                   \
+    return REF_OK;                                                                               \
+  }
+
+#define CAST_F32(x) ((float)(x))
+#define CAST_F64(x) ((double)(x))
+DEFINE_BACKWARD(ref_ggdt_backward_f32, float, edge_w_f32, CAST_F32)
+DEFINE_BACKWARD(ref_ggdt_backward_f64, double, edge_w_f64, CAST_F64)

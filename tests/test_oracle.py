@@ -1,0 +1,361 @@
+"""Pins for the CPU oracle (no GPU).
+
+The paper prints no numeric example, so the oracle is pinned to what the
+mathematics fixes:
+  * hand-worked tiny cases (tests/golden/hand_examples.json);
+  * the lambda = 0 closed form (king-move chains) after ONE iteration;
+  * bitwise equality of the converged schedule with multi-source Dijkstra,
+    in FP64 and in FP32;
+  * Dijkstra against exhaustive simple-path enumeration / bound-pruned walks;
+  * the non-converged schedule against a per-pass chain brute force that
+    evaluates every target on its own (no sweeping);
+  * invariants (seeds stay 0, 0 <= D <= v*M, monotone passes, scan >= Dijkstra,
+    fixed-point condition, flip symmetry at convergence);
+  * reverse-mode gradients against central finite differences.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_00001_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+def _eval(expr):
+    return float(eval(expr, {"__builtins__": {}}, {"sqrt": math.sqrt}))
+
+
+def _run_passes(image, mask, spacing, v, lam, npasses, precision="f64"):
+    nd = mask.ndim
+    D = (np.float64(v) * mask.astype(np.float64)) if precision == "f64" else (np.float32(v) * mask.astype(np.float32))
+    sched = oracle.pass_schedule(nd, (npasses + 2 * nd - 1) // (2 * nd))[:npasses]
+    for a, s in sched:
+        D = oracle.single_pass(image, D, spacing, lam, a, s, precision=precision)
+    return D
+
+
+# ------------------------------------------------------------ hand-worked cases
+
+def _golden_cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_hand_worked_examples(case):
+    image = np.array(case["image"], dtype=np.float64)
+    mask = np.array(case["mask"], dtype=np.float64)
+    for npass, expected in case["after_pass"].items():
+        exp = np.vectorize(_eval)(np.array(expected, dtype=object)).astype(np.float64)
+        got = _run_passes(image, mask, case["spacing"], case["v"], case["lam"], int(npass))
+        np.testing.assert_allclose(got, exp, rtol=1e-12, atol=1e-12, err_msg=f"after {npass} passes")
+    # the full schedule reproduces the last snapshot when it covers whole iterations
+    last = max(int(k) for k in case["after_pass"])
+    if last == case["iterations"] * 2 * mask.ndim:
+        full = oracle.ggdt(image, mask, case["spacing"], case["v"], case["lam"], case["iterations"], "f64")
+        exp = np.vectorize(_eval)(np.array(case["after_pass"][str(last)], dtype=object)).astype(np.float64)
+        np.testing.assert_allclose(full, exp, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------- lambda = 0 closed form
+
+@pytest.mark.parametrize("shape,spacing,seed", [
+    ((9, 11), (1.0, 1.0), 1),
+    ((10, 7), (0.7, 2.3), 2),
+    ((7, 8, 9), (1.0, 1.0, 2.5), 3),
+    ((6, 9, 5), (2.0, 0.5, 1.25), 4),
+    ((5, 5, 12), (3.0, 1.0, 0.6), 5),
+])
+def test_lambda0_closed_form_after_one_iteration(shape, spacing, seed):
+    rng = np.random.default_rng(seed)
+    mask = np.ones(shape)
+    for _ in range(3):
+        mask[tuple(rng.integers(0, s) for s in shape)] = 0.0
+    image = rng.random(shape)  # ignored by lambda = 0
+    got = oracle.ggdt(image, mask, spacing, 1e10, 0.0, 1, "f64")
+    exp = oracle.chamfer_closed_form(mask, spacing, 1e10)
+    rel = np.abs(got - exp) / np.maximum(exp, 1e-300)
+    assert rel.max() <= 1e-12
+    assert np.all(got[mask == 0] == 0.0)
+
+
+def test_lambda0_octile_2d_unit_spacing():
+    """2D unit spacing: the closed form is the octile distance max + (sqrt2 - 1) min."""
+    shape = (13, 17)
+    mask = np.ones(shape)
+    mask[4, 9] = 0
+    got = oracle.ggdt(np.zeros(shape), mask, (1, 1), 1e10, 0.0, 1, "f64")
+    yy, xx = np.mgrid[0:13, 0:17]
+    a, b = np.abs(yy - 4), np.abs(xx - 9)
+    exp = np.maximum(a, b) + (math.sqrt(2) - 1) * np.minimum(a, b)
+    np.testing.assert_allclose(got, exp, rtol=1e-12, atol=1e-14)
+
+
+# -------------------------------------------- converged schedule == Dijkstra bitwise
+
+def _maze(n=16, seed=0):
+    rng = np.random.default_rng(seed)
+    img = np.zeros((n, n), np.float32)
+    for r in range(2, n - 1, 4):
+        img[r, :] = 5.0
+        img[r, int(rng.integers(0, n))] = 0.0
+    for c in range(3, n - 1, 5):
+        img[:, c] = np.where(img[:, c] == 5.0, 5.0, img[:, c])
+    mask = np.ones((n, n), np.float32)
+    mask[0, 0] = 0.0
+    return img, mask
+
+
+CONVERGE_CASES = [
+    ("2d-c3", lambda: synth.small_case((14, 19), C=3, seed=11, lam=0.7)),
+    ("3d-c1", lambda: synth.small_case((7, 9, 8), C=1, seed=12, lam=0.7)),
+    ("3d-c2-soft", lambda: synth.small_case((6, 7, 8), C=2, seed=13, lam=0.4, soft=True, v=5.0)),
+    ("maze-lam1", lambda: dict(zip(("image", "mask"), _maze()), spacing=(1.0, 1.0), v=1e10, lam=1.0)),
+    ("maze-lam0.9", lambda: dict(zip(("image", "mask"), _maze(seed=3)), spacing=(1.0, 1.0), v=1e10, lam=0.9)),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,make", CONVERGE_CASES, ids=[c[0] for c in CONVERGE_CASES])
+def test_converged_scan_equals_dijkstra_bitwise(name, make, precision):
+    c = make()
+    D, n_it = oracle.until_converged(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision=precision)
+    Dj = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision=precision)
+    assert n_it >= 1
+    assert np.array_equal(D, Dj), f"max diff {np.abs(D.astype(np.float64) - Dj).max()}"
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_scan_never_below_dijkstra(precision):
+    c = synth.small_case((9, 8, 7), C=1, seed=21, lam=0.8)
+    Dj = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision=precision)
+    prev = None
+    for it in range(0, 4):
+        D = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], it, precision)
+        assert np.all(D >= Dj)
+        if prev is not None:
+            assert np.all(D <= prev)
+        prev = D
+
+
+# ------------------------------------------------------------- brute force paths
+
+@pytest.mark.parametrize("shape,lam,C", [((3, 4), 0.6, 1), ((4, 4), 1.0, 1), ((3, 3), 0.3, 2)])
+def test_dijkstra_equals_exhaustive_simple_paths(shape, lam, C):
+    c = synth.small_case(shape, C=C, seed=31, lam=lam)
+    bf = oracle.bruteforce_paths(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], prune=False)
+    Dj = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], "f64")
+    assert np.array_equal(bf, Dj)
+
+
+@pytest.mark.parametrize("shape,lam,soft", [((5, 5), 0.7, False), ((6, 6), 1.0, True), ((3, 3, 3), 0.5, False),
+                                            ((3, 4, 3), 0.9, True)])
+def test_dijkstra_equals_pruned_walks(shape, lam, soft):
+    c = synth.small_case(shape, C=1, seed=32, lam=lam, soft=soft, v=3.0 if soft else 1e10)
+    bf = oracle.bruteforce_paths(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], prune=True)
+    Dj = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], "f64")
+    assert np.array_equal(bf, Dj)
+    D, _ = oracle.until_converged(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision="f64")
+    assert np.array_equal(D, bf)
+
+
+# ------------------------------------------------- per-pass chain brute force
+
+@pytest.mark.parametrize("shape,C,lam,iters,soft", [
+    ((5, 5), 1, 0.7, 2, False),
+    ((4, 6), 2, 1.0, 2, True),
+    ((5, 4, 4), 1, 0.5, 1, False),
+    ((4, 4, 3), 1, 1.0, 2, True),
+    ((1, 6), 1, 0.3, 2, False),
+    ((3, 1, 4), 1, 0.6, 1, True),
+])
+def test_schedule_equals_composed_pass_bruteforce(shape, C, lam, iters, soft):
+    """Non-converged schedule: every pass equals the min over monotone chains,
+    composed in the canonical order; bitwise, and records say which chain won."""
+    c = synth.small_case(shape, C=C, seed=41, lam=lam, soft=soft, v=4.0 if soft else 1e10)
+    img = c["image"].astype(np.float64)
+    D = np.float64(c["v"]) * c["mask"].astype(np.float64)
+    for a, s in oracle.pass_schedule(len(shape), iters):
+        D = oracle.pass_bruteforce(img, D, c["spacing"], c["lam"], a, s)
+    ref = oracle.ggdt(img, c["mask"].astype(np.float64), c["spacing"], c["v"], c["lam"], iters, "f64")
+    assert np.array_equal(D, ref)
+
+
+def test_single_pass_records_reproduce_values():
+    """Record j on voxel x means D_new(x) = D_old(parent) + w (the parent value of this pass)."""
+    c = synth.small_case((6, 7, 5), C=2, seed=42, lam=0.6)
+    img = c["image"].astype(np.float64)
+    D0 = np.float64(c["v"]) * c["mask"].astype(np.float64)
+    D0 = oracle.single_pass(img, D0, c["spacing"], c["lam"], 0, 1, "f64")  # a non-trivial start
+    D1, rec = oracle.single_pass(img, D0, c["spacing"], c["lam"], 1, -1, "f64", records=True)
+    kept = rec == 0
+    assert np.array_equal(D1[kept], D0[kept])
+    assert np.all(D1[~kept] < D0[~kept])
+    assert np.all(rec[:, -1, :] == 0)  # first plane of a descending pass along axis 1
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_invariants_over_passes(precision):
+    c = synth.small_case((10, 9, 8), C=1, seed=51, lam=0.9)
+    img, mask = c["image"], c["mask"]
+    dt = np.float32 if precision == "f32" else np.float64
+    D = dt(c["v"]) * mask.astype(dt)
+    vm = D.copy()
+    for a, s in oracle.pass_schedule(3, 2):
+        Dn = oracle.single_pass(img, D, c["spacing"], c["lam"], a, s, precision)
+        assert np.all(Dn <= D)
+        assert np.all(Dn[mask == 0] == 0)
+        assert np.all((Dn >= 0) & (Dn <= vm))
+        D = Dn
+
+
+def test_constant_image_lambda1_gives_global_min():
+    shape = (6, 7, 5)
+    rng = np.random.default_rng(7)
+    mask = rng.uniform(0.2, 1.0, shape)
+    D, _ = oracle.until_converged(np.full(shape, 0.25), mask, (1, 2, 3), 2.0, 1.0, precision="f64")
+    assert np.all(D == 2.0 * mask.min())
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_fixed_point_condition_at_convergence(precision):
+    c = synth.small_case((11, 13), C=2, seed=61, lam=0.5)
+    D, _ = oracle.until_converged(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision=precision)
+    # one more pass of any direction changes nothing
+    for a, s in oracle.pass_schedule(2, 1):
+        assert np.array_equal(oracle.single_pass(c["image"], D, c["spacing"], c["lam"], a, s, precision), D)
+
+
+def test_flip_and_transpose_symmetry_at_convergence():
+    c = synth.small_case((7, 9, 6), C=1, seed=71, lam=0.8, spacing=(1.5, 1.5, 0.75))
+    img, mask = c["image"], c["mask"]
+    D, _ = oracle.until_converged(img, mask, c["spacing"], c["v"], c["lam"], precision="f64")
+    for ax in range(3):
+        Df, _ = oracle.until_converged(np.flip(img, ax + 1), np.flip(mask, ax), c["spacing"], c["v"], c["lam"],
+                                       precision="f64")
+        assert np.array_equal(np.flip(Df, ax), D)
+    Dt, _ = oracle.until_converged(np.swapaxes(img, 1, 2), np.swapaxes(mask, 0, 1), c["spacing"], c["v"],
+                                   c["lam"], precision="f64")
+    assert np.array_equal(np.swapaxes(Dt, 0, 1), D)
+
+
+def test_iterations_zero_and_unit_dims():
+    c = synth.small_case((5, 6), C=1, seed=81, lam=0.5)
+    D = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 0)
+    assert np.array_equal(D, np.float32(c["v"]) * c["mask"])
+    # a 1-wide axis: passes along it are no-ops, the other axis still propagates
+    img = np.arange(6, dtype=np.float32)[None, None, :]
+    m = np.ones((1, 6), np.float32)
+    m[0, 0] = 0
+    D = oracle.ggdt(img, m, (1, 1), 1e10, 1.0, 1)
+    assert np.array_equal(D[0], np.arange(6, dtype=np.float32))
+
+
+# ------------------------------------------------- the lambda = 1 fast-path identity
+
+def test_sqrt_of_square_is_abs_exhaustive():
+    """sqrtf(fl(d*d)) == |d| for every float32 d with 2^-63 <= |d| < 2^62 (correctly
+    rounded multiply and square root).  This is the identity that lets a single-channel
+    lambda = 1 pass use w = |d| without changing a single bit."""
+    lo = np.float32(2.0 ** -63).view(np.uint32)
+    hi = np.float32(2.0 ** 62).view(np.uint32)
+    step = 1 << 24
+    bad = 0
+    for start in range(int(lo), int(hi), step):
+        bits = np.arange(start, min(start + step, int(hi)), dtype=np.uint32)
+        d = bits.view(np.float32)
+        sq = d * d
+        bad += int(np.count_nonzero(np.sqrt(sq) != d))
+    assert bad == 0
+    # and it fails just below the range, which is why tiny values are routed elsewhere
+    d = np.float32(2.0 ** -70) * np.float32(1.3)
+    assert np.sqrt(d * d) != d
+
+
+def test_difference_range_argument():
+    """Differences of values that are 0 or have magnitude in [2^-40, 2^60] are 0 or have
+    magnitude in [2^-63, 2^61] (both operands are multiples of 2^-63)."""
+    rng = np.random.default_rng(5)
+    e = rng.uniform(-40, 60, size=200000)
+    a = (np.sign(rng.standard_normal(e.size)) * 2.0 ** e).astype(np.float32)
+    b = (a.view(np.uint32) + rng.integers(-3, 4, size=e.size).astype(np.uint32)).view(np.float32)
+    b = np.where(np.abs(b) < 2.0 ** -40, np.float32(0), b)
+    edges = np.array([2.0 ** -40, -2.0 ** -40, 0.0, np.nextafter(np.float32(2.0 ** -40), np.float32(1))],
+                     dtype=np.float32)
+    a = np.concatenate([a, np.repeat(edges, 4)])
+    b = np.concatenate([b, np.tile(edges, 4)])
+    d = np.abs(a - b)
+    ok = (d == 0) | ((d >= 2.0 ** -63) & (d <= 2.0 ** 61))
+    assert ok.all()
+
+
+# ---------------------------------------------------------------- gradients
+
+def _loss(image, mask, W, c, iters, precision="f64"):
+    D, rec = oracle.ggdt(image, mask, c["spacing"], c["v"], c["lam"], iters, precision, records=True)
+    return float(np.sum(W * D)), rec
+
+
+@pytest.mark.parametrize("shape,C,lam,iters", [((6, 7), 1, 0.7, 2), ((5, 6, 4), 1, 0.7, 2), ((6, 5), 2, 1.0, 1),
+                                               ((4, 5, 4), 2, 0.3, 2)])
+def test_backward_matches_central_differences(shape, C, lam, iters):
+    c = synth.small_case(shape, C=C, seed=91, lam=lam, soft=True, v=10.0)
+    img = c["image"].astype(np.float64)
+    mask = c["mask"].astype(np.float64)
+    W = np.random.default_rng(92).standard_normal(shape)
+    L0, rec0 = _loss(img, mask, W, c, iters)
+    gI, gM = oracle.backward(img, rec0, W, c["spacing"], c["v"], c["lam"], iters, "f64")
+    eps = 1e-6
+    rng = np.random.default_rng(93)
+    checked = 0
+    for _ in range(60):
+        idx = tuple(int(rng.integers(0, s)) for s in shape)
+        for which in ("M", "I"):
+            ch = int(rng.integers(0, C))
+            fwd = []
+            same = True
+            for sgn in (1, -1):
+                i2, m2 = img.copy(), mask.copy()
+                if which == "M":
+                    m2[idx] += sgn * eps
+                else:
+                    i2[(ch,) + idx] += sgn * eps
+                L, rec = _loss(i2, m2, W, c, iters)
+                same &= np.array_equal(rec, rec0)
+                fwd.append(L)
+            if not same:
+                continue  # too close to an argmin tie
+            fd = (fwd[0] - fwd[1]) / (2 * eps)
+            an = gM[idx] if which == "M" else gI[(ch,) + idx]
+            assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-6 * np.abs(W).max() * c["v"], (which, idx, an, fd)
+            checked += 1
+    assert checked >= 40
+
+
+def test_backward_f32_close_to_f64():
+    c = synth.small_case((6, 7, 5), C=1, seed=94, lam=0.7, soft=True, v=10.0)
+    W = np.random.default_rng(95).standard_normal(c["mask"].shape).astype(np.float32)
+    _, rec32 = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 2, "f32", records=True)
+    _, rec64 = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 2, "f64", records=True)
+    gI32, gM32 = oracle.backward(c["image"], rec32, W, c["spacing"], c["v"], c["lam"], 2, "f32")
+    gI64, gM64 = oracle.backward(c["image"], rec32, W, c["spacing"], c["v"], c["lam"], 2, "f64")
+    np.testing.assert_allclose(gM32, gM64, rtol=1e-4, atol=1e-4)
+    np.testing.assert_allclose(gI32, gI64, rtol=1e-4, atol=1e-4)
+    assert (rec32 == rec64).mean() > 0.99
+
+
+def test_backward_lambda0_has_no_image_gradient():
+    c = synth.small_case((5, 6), C=1, seed=96, lam=0.0, soft=True, v=10.0)
+    W = np.ones(c["mask"].shape)
+    _, rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], 0.0, 2, "f64", records=True)
+    gI, gM = oracle.backward(c["image"], rec, W, c["spacing"], c["v"], 0.0, 2, "f64")
+    assert np.all(gI == 0)
+    # every voxel's value is v*M of exactly one source, so the mask gradient sums to v * sum(W)
+    assert math.isclose(gM.sum(), c["v"] * W.sum(), rel_tol=1e-12)
