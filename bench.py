@@ -1,0 +1,156 @@
+"""Benchmark of the GGDT hot path on one MI355X.
+
+A step is one whole forward transform of the 3D workload: a 256^3 fp32 volume
+(C = 1), spacing (1, 1, 2.5), a 12^3 hard-seed cube, v = 1e10, lambda = 1,
+4 iterations of 6 directional passes, inputs resident in HBM.  The metric is
+voxel-updates/s = voxels x directional passes x iterations / time.
+
+Also reported (same JSON line):
+  roofline      the directional-pass kernel's algorithmic bytes (12 B per voxel
+                update: read I(x), read D_old(x), write D(x)) per launch over its
+                average launch duration, timed with HIP events on its stream,
+                against the MI355X HBM peak (8 TB/s); traffic from rocprofv3
+                counters when a summary for the current kernel source exists
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample: one
+                iteration (6 passes) of the same volume
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-updates/s + HBM GB/s vs peak, 3D 256³ GGDT; batched & backward vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_VU = 12  # lambda = 1, C = 1: image(x) 4 + D_old(x) 4 + D(x) 4
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pass_kernel_3d_256_pmc.json")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2208_00001_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_from_counters(n_voxels):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    with open(PMC_SUMMARY) as f:
+        s = json.load(f)
+    if s.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return s.get("hbm_bytes_per_pass_launch")
+
+
+def cpu_baseline(c):
+    import oracle
+    t = time.perf_counter()
+    oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
+    dt = time.perf_counter() - t
+    vu = c["mask"].size * 6
+    return {"value": vu / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 iteration (6 passes) of the {c['name']} volume, {vu} voxel-updates in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this path has no multi-GPU mode (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd import synth
+
+    B.load_library()
+    dev = "cuda:0"
+    c = synth.config3()
+    shape = c["mask"].shape
+    N = int(np.prod(shape))
+    passes = 6 * c["iterations"]
+    img = torch.from_numpy(c["image"]).to(dev)
+    m = torch.from_numpy(c["mask"]).to(dev)
+    out = torch.empty(shape, dtype=torch.float32, device=dev)
+    ws = B.new_workspace(shape, 1, dev)
+
+    def step():
+        B.ggdt3d(img, m, c["spacing"], c["v"], c["lam"], c["iterations"], out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert B.workspace_status(ws) == 0, "watchdog fired during warmup"
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    assert B.workspace_status(ws) == 0, "watchdog fired during the timed steps"
+    ms_per_step = ms_total / args.steps
+    vu_per_step = N * passes
+    value = vu_per_step / (ms_per_step * 1e-3)
+
+    # Pass-kernel durations: HIP events around each pass launch, on the launch stream.
+    B.profile_begin(args.steps * passes)
+    for _ in range(args.steps):
+        step()
+    durs = B.profile_end(args.steps * passes)
+    torch.cuda.synchronize()
+    avg_ms = float(np.mean(durs))
+    achieved = BYTES_PER_VU * N / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_counters(N)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": c["name"], "shape": list(shape), "channels": 1, "lambda": c["lam"], "v": c["v"],
+                   "spacing": list(c["spacing"]), "iterations": c["iterations"], "directional_passes": passes,
+                   "voxel_updates_per_step": vu_per_step, "seed": c["seed"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "directional pass (3D, lambda=1 C=1 path)", "bytes_per_voxel_update": BYTES_PER_VU,
+                     "launches_timed": len(durs), "avg_launch_ms": avg_ms},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(c)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

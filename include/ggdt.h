@@ -1,0 +1,198 @@
+/*
+ * ggdt.h — C ABI of the MI355X (gfx950) generalised geodesic distance transform.
+ *
+ * Method (FastGeodis paper, section "Implementation"; formula of the generalised
+ * GDT of Criminisi et al. 2008 that the paper implements, section "Statement of
+ * need"):
+ *
+ *   D0(x)   = v * M(x)                                   M: soft seed mask in [0, 1]
+ *   w(x, y) = sqrt((1 - lambda) * |x - y|_s^2 + lambda * sum_c (I_c(x) - I_c(y))^2)
+ *   a pass along axis a, direction +1 (ascending) or -1 (descending), visits the
+ *   rows (2D) / planes (3D) orthogonal to a in scan order; every voxel x of a
+ *   row/plane is updated in parallel from the 3 (2D) / 9 (3D) neighbours y in the
+ *   previous row/plane (already updated by this pass):
+ *       D(x) <- min(D(x), min_y D(y) + w(x, y))
+ *   one iteration = passes (axis 0, +1), (0, -1), (1, +1), (1, -1) [, (2, +1), (2, -1)].
+ *
+ * FP32 operation sequence (bitwise reproducible against a CPU implementation):
+ *   d_c = I_c(x) - I_c(y);  g = d_0 * d_0;  g = fmaf(d_c, d_c, g) (c = 1..C-1)
+ *   w = sqrtf(fmaf(lambda, g, A)),  A = (float)((1 - (double)lambda) * S),
+ *   S = sum over axes b ascending of (double(s_b) * |x_b - y_b|)^2 in double;
+ *   cand = D(y) + w; ties keep the current value, then the earlier offset in
+ *   lexicographic order over the non-scan axes (ascending axis, -1, 0, +1).
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers of the current HIP device, fp32,
+ *     C-contiguous (row-major): image (C, [D,] H, W), softmask and out ([D,] H, W).
+ *     spacing is a HOST pointer to ndim floats in array-axis order ([D,] H, W).
+ *   - All buffers are owned by the caller.  The library allocates no device memory
+ *     on these paths; per-call scratch lives in the caller's workspace.
+ *   - Work is enqueued on `stream` and runs asynchronously; the call returns after
+ *     validation and enqueueing.  Device-side faults surface at the next sync.
+ *   - Validation happens before anything is enqueued: on an error return nothing
+ *     has been written.
+ *   - Calls that share one workspace must not overlap in time (same stream, or
+ *     synchronised); distinct workspaces may run concurrently.
+ *   - No C++ exception crosses this boundary.
+ *
+ * Domain: v finite and >= 0, lambda in [0, 1], spacing finite and > 0,
+ * iterations >= 0, 1 <= C <= 16, every dimension >= 1.  Non-finite image or mask
+ * values are not rejected; results for them are unspecified.
+ */
+#ifndef GGDT_H_
+#define GGDT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  0 = success, negative = error. */
+#define GGDT_OK 0
+#define GGDT_ERR_NULL_PTR -1            /* a required pointer is NULL */
+#define GGDT_ERR_BAD_SHAPE -2           /* ndim, C or a dimension out of range, or size overflow */
+#define GGDT_ERR_BAD_PARAM -3           /* v, lambda, spacing or iterations outside the domain */
+#define GGDT_ERR_WORKSPACE_TOO_SMALL -4 /* workspace_bytes below the required size */
+#define GGDT_ERR_HIP -5                 /* a HIP runtime call or kernel launch failed */
+#define GGDT_ERR_WATCHDOG -6            /* a bounded inter-workgroup wait expired (see ggdt_workspace_status) */
+#define GGDT_ERR_ALIAS -7               /* an output overlaps an input */
+#define GGDT_ERR_UNSUPPORTED -8         /* valid request this build cannot run (e.g. no gfx950 device) */
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* ggdt_strerror(int status);
+
+/* Bytes of device workspace the forward and backward entry points need for a
+ * problem of `ndim` (2 or 3) spatial dims `dims` (array-axis order) and C
+ * channels.  Returns 0 for invalid shapes.  The workspace holds inter-workgroup
+ * progress flags, the image classification word and the watchdog word; its
+ * content need not be initialised by the caller. */
+size_t ggdt_workspace_bytes(int ndim, const int* dims, int C);
+
+/* Plain forward, 2D: out = GGDT(image, softmask) after `iterations` iterations of
+ * the four passes.  iterations = 0 writes v * softmask.  `out` must not overlap
+ * `image` or `softmask`. */
+int ggdt2d(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+           int iterations, float* out, int C, int H, int W, void* workspace, size_t workspace_bytes,
+           hipStream_t stream);
+
+/* Plain forward, 3D: as ggdt2d with six passes per iteration and spacing[3]. */
+int ggdt3d(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+           int iterations, float* out, int C, int D, int H, int W, void* workspace,
+           size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of argmin records for the forward-with-records entries:
+ * iterations * (2 * ndim) * prod(dims).  Layout: one byte per voxel per pass,
+ * pass-major (pass p = iteration * 2*ndim + 2*axis + (descending ? 1 : 0)), voxels
+ * row-major inside a pass.  Value 0 = the voxel kept its value in that pass;
+ * 1 + j = it took D(y) + w through offset j, where j enumerates the offsets over
+ * the non-scan axes lexicographically (ascending axis, components -1, 0, +1):
+ * j = delta_q + 1 in 2D, j = 3 * (delta_p + 1) + (delta_q + 1) in 3D, with p < q the
+ * non-scan axes and y = x - sign * e_axis + delta. */
+size_t ggdt_records_bytes(int ndim, const int* dims, int iterations);
+
+/* Forward that also writes the argmin records (device, ggdt_records_bytes bytes).
+ * `out` equals the plain forward's bit for bit. */
+int ggdt2d_forward_rec(const float* image, const float* softmask, const float* spacing, float v,
+                       float lambda, int iterations, float* out, uint8_t* records, int C, int H, int W,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+int ggdt3d_forward_rec(const float* image, const float* softmask, const float* spacing, float v,
+                       float lambda, int iterations, float* out, uint8_t* records, int C, int D, int H,
+                       int W, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Backward: exact reverse of the recorded schedule.  Given dL/dD (grad_out) and
+ * the records of the forward with the same image, spacing, v, lambda and
+ * iterations, writes dL/dI (grad_image, shape of image) and dL/dM (grad_softmask,
+ * shape of softmask).  Where w = 0 the derivative of w is taken as 0.
+ * grad_softmask doubles as the adjoint accumulator; outputs must not overlap the
+ * inputs or each other. */
+int ggdt2d_backward(const float* image, const uint8_t* records, const float* grad_out,
+                    const float* spacing, float v, float lambda, int iterations, float* grad_image,
+                    float* grad_softmask, int C, int H, int W, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+int ggdt3d_backward(const float* image, const uint8_t* records, const float* grad_out,
+                    const float* spacing, float v, float lambda, int iterations, float* grad_image,
+                    float* grad_softmask, int C, int D, int H, int W, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
+/* After the stream has finished a call, report whether its inter-workgroup waits
+ * all completed: synchronises `stream`, returns GGDT_OK or GGDT_ERR_WATCHDOG (the
+ * results of that call are then invalid).  `workspace` is the one the call used. */
+int ggdt_workspace_status(const void* workspace, hipStream_t stream);
+
+/* Debug knob: upper bound on polls of one inter-workgroup wait before the
+ * watchdog fires (default 2^21).  Process-wide; 0 restores the default. */
+void ggdt_set_spin_limit(unsigned long long polls);
+
+/* Profiling (process-wide, not thread-safe).  After ggdt_profile_begin(n) the
+ * forward and backward entry points record a HIP event pair on their stream
+ * around each of their next n directional-pass kernel launches.
+ * ggdt_profile_end synchronises those events, writes up to `capacity` launch
+ * durations in milliseconds to `ms` (host) and returns how many launches were
+ * recorded (or a negative status); it also ends profiling.  Begin allocates host
+ * event objects only. */
+int ggdt_profile_begin(int n);
+int ggdt_profile_end(float* ms, int capacity);
+
+/* ------------------------------------------------------------------ batched */
+
+/* One instance of a ragged batch.  Same meaning and layout as the plain entry
+ * points; dims[2] is ignored for ndim = 2; records may be NULL (then the backward
+ * cannot run for this instance).  grad_* are used only by
+ * ggdt_batched_backward and may be NULL otherwise. */
+typedef struct ggdt_instance {
+  int ndim;
+  int C;
+  int dims[3];
+  const float* image;
+  const float* softmask;
+  float* out;
+  float spacing[3];
+  float v;
+  float lambda;
+  int iterations;
+  uint8_t* records;
+  const float* grad_out;
+  float* grad_image;
+  float* grad_softmask;
+} ggdt_instance;
+
+typedef struct ggdt_plan ggdt_plan;
+
+/* Build a plan for n instances: validates every instance, splits the device's
+ * resident workgroup slots among them and lays out the device descriptor table.
+ * `tuning` (nullable) overrides tile geometry: see ggdt_tuning.  Writes the
+ * workspace size the plan needs.  The plan (host object) is owned by the library
+ * until ggdt_plan_destroy.  Errors are those of the plain entries, for the first
+ * offending instance. */
+typedef struct ggdt_tuning {
+  int tile_p;      /* 3D plane tile rows (0 = default) */
+  int tile_q;      /* 3D plane tile width / 2D row tile width (0 = default) */
+  int chunk;       /* scan steps between inter-workgroup syncs (0 = default) */
+  int wg_per_cu;   /* resident workgroups per compute unit to plan for (0 = default) */
+} ggdt_tuning;
+
+int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* tuning, ggdt_plan** plan,
+                      size_t* workspace_bytes);
+
+/* Run every instance's forward (records written where non-NULL) in one
+ * persistent launch on `stream`.  Performs no host synchronisation and no
+ * allocation, so it can be captured into a HIP graph; the plan's device table is
+ * uploaded by ggdt_batched_plan. */
+int ggdt_batched_run(const ggdt_plan* plan, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Run every instance's backward in one persistent launch (all instances need
+ * records, grad_out, grad_image and grad_softmask). */
+int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+void ggdt_plan_destroy(ggdt_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GGDT_H_ */

@@ -1,0 +1,251 @@
+"""ctypes binding of libggdt.so: argument marshalling only.
+
+PyTorch provides device memory and the HIP stream (torch's current stream);
+every step of the transform runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is missing or the device is not gfx950, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libggdt.so")
+
+GGDT_OK = 0
+_c_int, _c_float, _c_size, _vp = ctypes.c_int, ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p
+
+
+class GGDTError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = _lib.ggdt_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} (status {code})")
+
+
+class GGDTInstance(ctypes.Structure):
+    _fields_ = [
+        ("ndim", _c_int), ("C", _c_int), ("dims", _c_int * 3),
+        ("image", _vp), ("softmask", _vp), ("out", _vp),
+        ("spacing", _c_float * 3), ("v", _c_float), ("lam", _c_float), ("iterations", _c_int),
+        ("records", _vp), ("grad_out", _vp), ("grad_image", _vp), ("grad_softmask", _vp),
+    ]
+
+
+class GGDTTuning(ctypes.Structure):
+    _fields_ = [("tile_p", _c_int), ("tile_q", _c_int), ("chunk", _c_int), ("wg_per_cu", _c_int)]
+
+
+_lib = None
+
+_SIGS = {
+    "ggdt_strerror": (ctypes.c_char_p, [_c_int]),
+    "ggdt_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt_records_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt2d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp, _c_size, _vp]),
+    "ggdt3d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int, _vp, _c_size,
+                        _vp]),
+    "ggdt2d_forward_rec": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _vp, _c_int, _c_int, _c_int, _vp,
+                                    _c_size, _vp]),
+    "ggdt3d_forward_rec": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _vp, _c_int, _c_int, _c_int,
+                                    _c_int, _vp, _c_size, _vp]),
+    "ggdt2d_backward": (_c_int, [_vp, _vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _vp, _c_int, _c_int, _c_int,
+                                 _vp, _c_size, _vp]),
+    "ggdt3d_backward": (_c_int, [_vp, _vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _vp, _c_int, _c_int, _c_int,
+                                 _c_int, _vp, _c_size, _vp]),
+    "ggdt_workspace_status": (_c_int, [_vp, _vp]),
+    "ggdt_set_spin_limit": (None, [ctypes.c_ulonglong]),
+    "ggdt_profile_begin": (_c_int, [_c_int]),
+    "ggdt_profile_end": (_c_int, [_vp, _c_int]),
+    "ggdt_batched_plan": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "ggdt_batched_run": (_c_int, [_vp, _vp, _c_size, _vp]),
+    "ggdt_batched_backward": (_c_int, [_vp, _vp, _c_size, _vp]),
+    "ggdt_plan_destroy": (None, [_vp]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libggdt.so (after torch, so both use torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run paper_2208_00001_amd.build.build() (or __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dims(shape):
+    return (ctypes.c_int * len(shape))(*shape)
+
+
+def _prep(image: torch.Tensor, softmask: torch.Tensor):
+    if not (image.is_cuda and softmask.is_cuda):
+        raise ValueError("image and softmask must be device tensors")
+    if image.dtype != torch.float32 or softmask.dtype != torch.float32:
+        raise TypeError("image and softmask must be float32")
+    spatial = tuple(softmask.shape)
+    if image.dim() == len(spatial):
+        image = image.unsqueeze(0)
+    if tuple(image.shape[1:]) != spatial or len(spatial) not in (2, 3):
+        raise ValueError(f"shape mismatch: image {tuple(image.shape)} vs softmask {spatial}")
+    return image.contiguous(), softmask.contiguous(), spatial
+
+
+def workspace_bytes(spatial: Sequence[int], C: int) -> int:
+    lib = load_library()
+    return int(lib.ggdt_workspace_bytes(len(spatial), _dims(spatial), C))
+
+
+def records_bytes(spatial: Sequence[int], iterations: int) -> int:
+    lib = load_library()
+    return int(lib.ggdt_records_bytes(len(spatial), _dims(spatial), iterations))
+
+
+def new_workspace(spatial, C, device) -> torch.Tensor:
+    n = workspace_bytes(spatial, C)
+    if n == 0:
+        raise ValueError(f"invalid shape {tuple(spatial)} with C={C}")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _spacing(spacing, nd):
+    sp = tuple(float(s) for s in spacing)
+    if len(sp) != nd:
+        raise ValueError(f"spacing needs {nd} values")
+    return (ctypes.c_float * nd)(*sp)
+
+
+def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records):
+    lib = load_library()
+    image, softmask, spatial = _prep(image, softmask)
+    nd, C = len(spatial), image.shape[0]
+    if out is None:
+        out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    if workspace is None:
+        workspace = new_workspace(spatial, C, softmask.device)
+    sp = _spacing(spacing, nd)
+    args = [_ptr(image), _ptr(softmask), sp, float(v), float(lamb), int(iterations), _ptr(out)]
+    if records is not None:
+        args.append(_ptr(records))
+    args += [C, *spatial, _ptr(workspace), workspace.numel(), _stream()]
+    if records is None:
+        fn = lib.ggdt2d if nd == 2 else lib.ggdt3d
+    else:
+        fn = lib.ggdt2d_forward_rec if nd == 2 else lib.ggdt3d_forward_rec
+    rc = fn(*args)
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    return out
+
+
+def ggdt2d(image, softmask, spacing=(1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
+    """2D GGDT of image (C, H, W) or (H, W) with soft seed mask (H, W); returns D (H, W)."""
+    if softmask.dim() != 2:
+        raise ValueError("softmask must be (H, W)")
+    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None)
+
+
+def ggdt3d(image, softmask, spacing=(1.0, 1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
+    """3D GGDT of image (C, D, H, W) or (D, H, W) with soft seed mask (D, H, W); returns D."""
+    if softmask.dim() != 3:
+        raise ValueError("softmask must be (D, H, W)")
+    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None)
+
+
+def ggdt_forward_rec(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, records=None,
+                     workspace=None):
+    """Forward that also returns the argmin records, uint8 (passes, *spatial)."""
+    _, sm, spatial = _prep(image, softmask)
+    npass = iterations * 2 * len(spatial)
+    if records is None:
+        records = torch.empty((npass,) + spatial, dtype=torch.uint8, device=sm.device)
+    out = _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records)
+    return out, records
+
+
+def ggdt_backward(image, records, grad_out, spacing, v, lamb, iterations, workspace=None):
+    """Reverse of the recorded schedule: returns (dL/dI with image's shape, dL/dM)."""
+    lib = load_library()
+    squeeze = image.dim() == grad_out.dim()
+    image, grad_out, spatial = _prep(image, grad_out)
+    nd, C = len(spatial), image.shape[0]
+    if records.dtype != torch.uint8 or not records.is_cuda:
+        raise TypeError("records must be a uint8 device tensor")
+    gi = torch.empty_like(image)
+    gm = torch.empty(spatial, dtype=torch.float32, device=image.device)
+    if workspace is None:
+        workspace = new_workspace(spatial, C, image.device)
+    fn = lib.ggdt2d_backward if nd == 2 else lib.ggdt3d_backward
+    rc = fn(_ptr(image), _ptr(records.contiguous()), _ptr(grad_out), _spacing(spacing, nd), float(v), float(lamb),
+            int(iterations), _ptr(gi), _ptr(gm), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    return (gi[0] if squeeze else gi), gm
+
+
+def workspace_status(workspace) -> int:
+    lib = load_library()
+    return int(lib.ggdt_workspace_status(_ptr(workspace), _stream()))
+
+
+def profile_begin(n: int) -> None:
+    rc = load_library().ggdt_profile_begin(int(n))
+    if rc != GGDT_OK:
+        raise GGDTError(rc, "ggdt_profile_begin")
+
+
+def profile_end(capacity: int):
+    """Durations (ms) of the pass kernels launched since profile_begin."""
+    buf = (ctypes.c_float * max(1, capacity))()
+    n = load_library().ggdt_profile_end(buf, capacity)
+    if n < 0:
+        raise GGDTError(n, "ggdt_profile_end")
+    return [buf[i] for i in range(min(n, capacity))]
+
+
+def set_spin_limit(polls: int) -> None:
+    load_library().ggdt_set_spin_limit(int(polls))
+
+
+class GGDTFunction(torch.autograd.Function):
+    """D = GGDT(image, softmask) with gradients for image and softmask."""
+
+    @staticmethod
+    def forward(ctx, image, softmask, spacing, v, lamb, iterations):
+        out, rec = ggdt_forward_rec(image.detach(), softmask.detach(), spacing, v, lamb, iterations)
+        ctx.save_for_backward(image.detach(), rec)
+        ctx.params = (tuple(spacing), float(v), float(lamb), int(iterations))
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        image, rec = ctx.saved_tensors
+        spacing, v, lamb, iterations = ctx.params
+        gi, gm = ggdt_backward(image, rec, grad_out.contiguous().float(), spacing, v, lamb, iterations)
+        return gi, gm, None, None, None, None
+
+
+def ggdt_batched(*args, **kwargs):  # defined in batched.py once available
+    from . import batched
+    return batched.ggdt_batched(*args, **kwargs)
+
+
+def BatchedPlan(*args, **kwargs):
+    from . import batched
+    return batched.BatchedPlan(*args, **kwargs)

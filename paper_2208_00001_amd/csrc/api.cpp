@@ -1,0 +1,386 @@
+// C ABI of the GGDT library: argument validation, per-pass parameter preparation
+// (edge-constant table) and the pass schedule.  Every step of the transform runs
+// in the HIP kernels; this file only prepares launches.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ggdt.h"
+#include "ggdt_api_internal.h"
+#include "ggdt_internal.h"
+
+namespace ggdt {
+
+unsigned long long g_spin_limit = kDefaultSpinLimit;
+
+namespace {
+hipEvent_t* g_prof_events = nullptr;
+int g_prof_cap = 0;
+int g_prof_used = 0;
+}  // namespace
+
+hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, unsigned* flags, hipStream_t stream) {
+  const bool prof = g_prof_events && g_prof_used < g_prof_cap;
+  if (prof) hipEventRecord(g_prof_events[2 * g_prof_used], stream);
+  const hipError_t e = launch_pass(d, ndim, words, flags, g_spin_limit, 0, stream);
+  if (prof) hipEventRecord(g_prof_events[2 * g_prof_used++ + 1], stream);
+  return e;
+}
+
+const char* status_text(int status) {
+  switch (status) {
+    case GGDT_OK: return "ok";
+    case GGDT_ERR_NULL_PTR: return "a required pointer is NULL";
+    case GGDT_ERR_BAD_SHAPE: return "invalid shape (ndim, C or a dimension out of range, or size overflow)";
+    case GGDT_ERR_BAD_PARAM: return "invalid parameter (v, lambda, spacing or iterations outside the domain)";
+    case GGDT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case GGDT_ERR_HIP: return "HIP runtime error";
+    case GGDT_ERR_WATCHDOG: return "an inter-workgroup wait expired (watchdog)";
+    case GGDT_ERR_ALIAS: return "an output overlaps an input";
+    case GGDT_ERR_UNSUPPORTED: return "unsupported request or device (needs gfx950)";
+    default: return "unknown status";
+  }
+}
+
+int check_device() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GGDT_ERR_HIP;
+  if (cached[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GGDT_ERR_HIP;
+    cached[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+  }
+  return cached[dev] == 1 ? GGDT_OK : GGDT_ERR_UNSUPPORTED;
+}
+
+int make_problem(int ndim, const int* dims, int C, Problem* pr) {
+  if (ndim != 2 && ndim != 3) return GGDT_ERR_BAD_SHAPE;
+  if (C < 1 || C > kMaxChannels) return GGDT_ERR_BAD_SHAPE;
+  long long n = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (dims[i] < 1) return GGDT_ERR_BAD_SHAPE;
+    n *= dims[i];
+    if (n > 0x7fffffffLL) return GGDT_ERR_BAD_SHAPE;
+  }
+  if (n * C > (1LL << 40)) return GGDT_ERR_BAD_SHAPE;
+  pr->ndim = ndim;
+  pr->C = C;
+  pr->N = n;
+  for (int i = 0; i < 3; ++i) pr->dims[i] = i < ndim ? dims[i] : 1;
+  return GGDT_OK;
+}
+
+int check_params(int ndim, const float* spacing, float v, float lam, int iterations) {
+  if (!spacing) return GGDT_ERR_NULL_PTR;
+  if (!(isfinite(v) && v >= 0.0f)) return GGDT_ERR_BAD_PARAM;
+  if (!(lam >= 0.0f && lam <= 1.0f)) return GGDT_ERR_BAD_PARAM;
+  if (iterations < 0) return GGDT_ERR_BAD_PARAM;
+  for (int b = 0; b < ndim; ++b)
+    if (!(isfinite(spacing[b]) && spacing[b] > 0.0f)) return GGDT_ERR_BAD_PARAM;
+  return GGDT_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+int check_alias(const void* out, size_t nout, const void* const* ins, const size_t* nins, int nin) {
+  for (int i = 0; i < nin; ++i)
+    if (overlaps(out, nout, ins[i], nins[i])) return GGDT_ERR_ALIAS;
+  return GGDT_OK;
+}
+
+void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ, int* K) {
+  if (pr.ndim == 3) {
+    *TP = kTileP3;
+    *TQ = kTileQ3;
+    int k = tu.chunk > 0 ? tu.chunk : kChunk3;
+    if (k > kTileP3) k = kTileP3;
+    // keep the LDS planes (2 + 2C) * (TP + 2K) * (TQ + 2K) floats within 64 KiB
+    while (k > 1 && (size_t)(2 + 2 * pr.C) * (kTileP3 + 2 * k) * (kTileQ3 + 2 * k) * 4 > 65536) --k;
+    *K = k;
+  } else {
+    *TP = 1;
+    *TQ = kTileQ2;
+    int k = tu.chunk > 0 ? tu.chunk : kChunk2;
+    if (k > kTileQ2) k = kTileQ2;
+    while (k > 1 && (size_t)(2 + 2 * pr.C) * (kTileQ2 + 2 * k) * 4 > 65536) --k;
+    *K = k;
+  }
+}
+
+// Geometry of a pass along `axis`: p, q are the non-scan axes in ascending order.
+void pass_geometry(const Problem& pr, int axis, PassDesc* d) {
+  long long stride[3];
+  stride[pr.ndim - 1] = 1;
+  for (int b = pr.ndim - 2; b >= 0; --b) stride[b] = stride[b + 1] * pr.dims[b + 1];
+  int other[2], no = 0;
+  for (int b = 0; b < pr.ndim; ++b)
+    if (b != axis) other[no++] = b;
+  d->Na = pr.dims[axis];
+  d->sa = (int)stride[axis];
+  if (pr.ndim == 3) {
+    d->Np = pr.dims[other[0]];
+    d->sp = (int)stride[other[0]];
+    d->Nq = pr.dims[other[1]];
+    d->sq = (int)stride[other[1]];
+  } else {
+    d->Np = 1;
+    d->sp = 0;
+    d->Nq = pr.dims[other[0]];
+    d->sq = (int)stride[other[0]];
+  }
+}
+
+// Edge constants of a pass along `axis`: A_j = (float)((1 - lambda) * S_j) with
+// S_j = sum over axes b ascending of (s_b * |dx_b|)^2 in double, where the offset
+// j has |dx| = 1 on the scan axis and (delta_p, delta_q) on the others.
+void edge_constants(const Problem& pr, int axis, const float* spacing, float lam, float* A, float* W0) {
+  int other[2], no = 0;
+  for (int b = 0; b < pr.ndim; ++b)
+    if (b != axis) other[no++] = b;
+  const int nj = pr.ndim == 3 ? 9 : 3;
+  for (int j = 0; j < 9; ++j) {
+    A[j] = 0.0f;
+    W0[j] = 0.0f;
+  }
+  for (int j = 0; j < nj; ++j) {
+    int dx[3] = {0, 0, 0};
+    dx[axis] = 1;
+    if (pr.ndim == 3) {
+      dx[other[0]] = j / 3 - 1;
+      dx[other[1]] = j % 3 - 1;
+    } else {
+      dx[other[0]] = j - 1;
+    }
+    double S = 0.0;
+    for (int b = 0; b < pr.ndim; ++b) {
+      const double t = (double)spacing[b] * (double)abs(dx[b]);
+      S = S + t * t;
+    }
+    A[j] = (float)((1.0 - (double)lam) * S);
+    W0[j] = sqrtf(A[j]);
+  }
+}
+
+int requested_mode(float lam, int C) {
+  if (lam == 0.0f) return kModeLam0;
+  if (lam == 1.0f && C == 1) return kModeLam1C1;
+  return kModeGeneral;
+}
+
+int max_tiles(const Problem& pr, const Tuning& tu) {
+  int TP, TQ, K;
+  tile_shape(pr, tu, &TP, &TQ, &K);
+  int best = 1;
+  for (int a = 0; a < pr.ndim; ++a) {
+    PassDesc d;
+    pass_geometry(pr, a, &d);
+    const int nt = ((d.Np + TP - 1) / TP) * ((d.Nq + TQ - 1) / TQ);
+    if (nt > best) best = nt;
+  }
+  return best;
+}
+
+size_t workspace_for(const Problem& pr, const Tuning& tu) {
+  const size_t flags = ((size_t)max_tiles(pr, tu) * 4 + 255) / 256 * 256;
+  return (size_t)kHeaderWords * 4 + flags;
+}
+
+// Enqueue the whole forward schedule of one instance.
+int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
+                    float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
+                    hipStream_t stream) {
+  unsigned* words = (unsigned*)ws;
+  unsigned* flags = words + kHeaderWords;
+  const int nflag_words = (int)((workspace_for(pr, tu) - kHeaderWords * 4) / 4);
+  if (launch_reset(words, kHeaderWords + nflag_words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (iterations == 0) {
+    if (launch_scale(mask, v, out, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
+    return GGDT_OK;
+  }
+  const int mode = requested_mode(lam, pr.C);
+  if (mode != kModeGeneral) {
+    if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  }
+  int TP, TQ, K;
+  tile_shape(pr, tu, &TP, &TQ, &K);
+  unsigned base = 0;
+  int p = 0;
+  for (int it = 0; it < iterations; ++it) {
+    for (int a = 0; a < pr.ndim; ++a) {
+      PassDesc d;
+      memset(&d, 0, sizeof d);
+      pass_geometry(pr, a, &d);
+      edge_constants(pr, a, spacing, lam, d.A, d.W0);
+      d.image = image;
+      d.mask = mask;
+      d.D = out;
+      d.N = (int)pr.N;
+      d.C = pr.C;
+      d.TP = TP;
+      d.TQ = TQ;
+      d.K = K;
+      d.ntp = (d.Np + TP - 1) / TP;
+      d.ntq = (d.Nq + TQ - 1) / TQ;
+      d.nchunk = (d.Na - 1 + K - 1) / K;
+      d.mode = mode;
+      d.v = v;
+      d.lam = lam;
+      for (int s = 0; s < 2; ++s, ++p) {
+        d.sign = s == 0 ? 1 : -1;
+        d.init = p == 0 ? 1 : 0;
+        d.rec = records ? records + (size_t)p * pr.N : nullptr;
+        d.flag_base = base;
+        base += (unsigned)d.nchunk + 1u;
+        if (launch_pass_profiled(d, pr.ndim, words, flags, stream) != hipSuccess) return GGDT_ERR_HIP;
+      }
+    }
+  }
+  return GGDT_OK;
+}
+
+int forward_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
+                  float v, float lam, int iterations, float* out, uint8_t* records, bool want_records, void* ws,
+                  size_t wsb, hipStream_t stream) {
+  if (!image || !mask || !out || !ws || !dims) return GGDT_ERR_NULL_PTR;
+  if (want_records && !records) return GGDT_ERR_NULL_PTR;
+  Problem pr;
+  int rc = make_problem(ndim, dims, C, &pr);
+  if (rc) return rc;
+  rc = check_params(ndim, spacing, v, lam, iterations);
+  if (rc) return rc;
+  const Tuning tu{};
+  if (wsb < workspace_for(pr, tu)) return GGDT_ERR_WORKSPACE_TOO_SMALL;
+  const size_t nb = (size_t)pr.N * 4, ni = (size_t)pr.N * pr.C * 4;
+  const size_t nrec = want_records ? (size_t)iterations * 2 * ndim * pr.N : 0;
+  const void* ins[3] = {image, mask, ws};
+  const size_t nins[3] = {ni, nb, wsb};
+  rc = check_alias(out, nb, ins, nins, 3);
+  if (rc) return rc;
+  if (want_records) {
+    const void* ins2[4] = {image, mask, ws, out};
+    const size_t nins2[4] = {ni, nb, wsb, nb};
+    rc = check_alias(records, nrec, ins2, nins2, 4);
+    if (rc) return rc;
+  }
+  rc = check_device();
+  if (rc) return rc;
+  return enqueue_forward(pr, image, mask, spacing, v, lam, iterations, out, want_records ? records : nullptr, ws,
+                         tu, stream);
+}
+
+}  // namespace ggdt
+
+using namespace ggdt;
+
+extern "C" {
+
+const char* ggdt_strerror(int status) { return status_text(status); }
+
+size_t ggdt_workspace_bytes(int ndim, const int* dims, int C) {
+  if (!dims) return 0;
+  Problem pr;
+  if (make_problem(ndim, dims, C, &pr)) return 0;
+  return workspace_for(pr, Tuning{});
+}
+
+size_t ggdt_records_bytes(int ndim, const int* dims, int iterations) {
+  if (!dims || iterations < 0) return 0;
+  Problem pr;
+  if (make_problem(ndim, dims, 1, &pr)) return 0;
+  return (size_t)iterations * 2 * ndim * (size_t)pr.N;
+}
+
+int ggdt2d(const float* image, const float* softmask, const float* spacing, float v, float lambda, int iterations,
+           float* out, int C, int H, int W, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  const int dims[2] = {H, W};
+  return forward_entry(2, dims, C, image, softmask, spacing, v, lambda, iterations, out, nullptr, false, workspace,
+                       workspace_bytes, stream);
+}
+
+int ggdt3d(const float* image, const float* softmask, const float* spacing, float v, float lambda, int iterations,
+           float* out, int C, int D, int H, int W, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  const int dims[3] = {D, H, W};
+  return forward_entry(3, dims, C, image, softmask, spacing, v, lambda, iterations, out, nullptr, false, workspace,
+                       workspace_bytes, stream);
+}
+
+int ggdt2d_forward_rec(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                       int iterations, float* out, uint8_t* records, int C, int H, int W, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+  const int dims[2] = {H, W};
+  return forward_entry(2, dims, C, image, softmask, spacing, v, lambda, iterations, out, records, true, workspace,
+                       workspace_bytes, stream);
+}
+
+int ggdt3d_forward_rec(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                       int iterations, float* out, uint8_t* records, int C, int D, int H, int W, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+  const int dims[3] = {D, H, W};
+  return forward_entry(3, dims, C, image, softmask, spacing, v, lambda, iterations, out, records, true, workspace,
+                       workspace_bytes, stream);
+}
+
+int ggdt_workspace_status(const void* workspace, hipStream_t stream) {
+  if (!workspace) return GGDT_ERR_NULL_PTR;
+  if (hipStreamSynchronize(stream) != hipSuccess) return GGDT_ERR_HIP;
+  unsigned word = 0;
+  if (hipMemcpy(&word, workspace, sizeof word, hipMemcpyDeviceToHost) != hipSuccess) return GGDT_ERR_HIP;
+  return word ? GGDT_ERR_WATCHDOG : GGDT_OK;
+}
+
+void ggdt_set_spin_limit(unsigned long long polls) { g_spin_limit = polls ? polls : kDefaultSpinLimit; }
+
+static void profile_free() {
+  if (g_prof_events) {
+    for (int i = 0; i < 2 * g_prof_cap; ++i) hipEventDestroy(g_prof_events[i]);
+    free(g_prof_events);
+  }
+  g_prof_events = nullptr;
+  g_prof_cap = 0;
+  g_prof_used = 0;
+}
+
+int ggdt_profile_begin(int n) {
+  profile_free();
+  if (n <= 0) return GGDT_ERR_BAD_PARAM;
+  hipEvent_t* ev = (hipEvent_t*)calloc((size_t)2 * n, sizeof(hipEvent_t));
+  if (!ev) return GGDT_ERR_HIP;
+  for (int i = 0; i < 2 * n; ++i) {
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
+      free(ev);
+      return GGDT_ERR_HIP;
+    }
+  }
+  g_prof_events = ev;
+  g_prof_cap = n;
+  g_prof_used = 0;
+  return GGDT_OK;
+}
+
+int ggdt_profile_end(float* ms, int capacity) {
+  if (!g_prof_events) return 0;
+  const int used = g_prof_used;
+  int rc = used;
+  for (int i = 0; i < used; ++i) {
+    if (hipEventSynchronize(g_prof_events[2 * i + 1]) != hipSuccess) {
+      rc = GGDT_ERR_HIP;
+      break;
+    }
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, g_prof_events[2 * i], g_prof_events[2 * i + 1]) != hipSuccess) {
+      rc = GGDT_ERR_HIP;
+      break;
+    }
+    if (ms && i < capacity) ms[i] = t;
+  }
+  profile_free();
+  return rc;
+}
+
+}  // extern "C"

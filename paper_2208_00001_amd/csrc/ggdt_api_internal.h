@@ -1,0 +1,48 @@
+// Host-side helpers shared by the C-ABI sources (not part of the C ABI).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "ggdt_internal.h"
+
+namespace ggdt {
+
+constexpr int kMaxChannels = 16;
+constexpr unsigned long long kDefaultSpinLimit = 1ull << 21;
+constexpr int kTileP3 = 16, kTileQ3 = 16, kChunk3 = 8;  // 3D plane tile and chunk
+constexpr int kTileQ2 = 256, kChunk2 = 32;              // 2D row tile and chunk
+
+extern unsigned long long g_spin_limit;
+
+struct Problem {
+  int ndim;
+  int dims[3];
+  int C;
+  long long N;
+};
+
+struct Tuning {
+  int tile_p = 0;
+  int tile_q = 0;
+  int chunk = 0;
+  int wg_per_cu = 0;
+};
+
+const char* status_text(int status);
+// Launch a pass kernel, recording profiling events around it when profiling is on.
+hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, unsigned* flags, hipStream_t stream);
+int check_device();
+int make_problem(int ndim, const int* dims, int C, Problem* pr);
+int check_params(int ndim, const float* spacing, float v, float lam, int iterations);
+int check_alias(const void* out, size_t nout, const void* const* ins, const size_t* nins, int nin);
+void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ, int* K);
+void pass_geometry(const Problem& pr, int axis, PassDesc* d);
+void edge_constants(const Problem& pr, int axis, const float* spacing, float lam, float* A, float* W0);
+int requested_mode(float lam, int C);
+int max_tiles(const Problem& pr, const Tuning& tu);
+size_t workspace_for(const Problem& pr, const Tuning& tu);
+
+}  // namespace ggdt

@@ -1,0 +1,102 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/ggdt.h declares, and rejects invalid arguments with the
+documented status before touching the device (fake device pointers are never
+dereferenced on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ggdt.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (load torch's HIP runtime first, as the binding does)
+    from paper_2208_00001_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2208_00001_amd import build
+        build.build()
+    return binding.load_library()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(ggdt_?\w*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ["ggdt2d", "ggdt3d", "ggdt_workspace_bytes", "ggdt_records_bytes", "ggdt2d_forward_rec",
+              "ggdt3d_forward_rec", "ggdt2d_backward", "ggdt3d_backward", "ggdt_batched_plan", "ggdt_batched_run",
+              "ggdt_batched_backward", "ggdt_plan_destroy", "ggdt_strerror", "ggdt_workspace_status",
+              "ggdt_set_spin_limit"]:
+        assert n in names, n
+
+
+def test_library_exports_every_declared_function(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_total(lib):
+    for code in range(-9, 1):
+        assert lib.ggdt_strerror(code)
+    assert lib.ggdt_strerror(0) == b"ok"
+
+
+def test_sizes(lib):
+    dims = (ctypes.c_int * 3)(256, 256, 256)
+    assert lib.ggdt_records_bytes(3, dims, 4) == 4 * 6 * 256 ** 3
+    assert lib.ggdt_workspace_bytes(3, dims, 1) >= 256 + 4 * 256
+    assert lib.ggdt_workspace_bytes(3, dims, 0) == 0
+    assert lib.ggdt_workspace_bytes(3, dims, 17) == 0
+    bad = (ctypes.c_int * 3)(0, 4, 4)
+    assert lib.ggdt_workspace_bytes(3, bad, 1) == 0
+    assert lib.ggdt_workspace_bytes(4, dims, 1) == 0
+    huge = (ctypes.c_int * 3)(2048, 2048, 1024)
+    assert lib.ggdt_workspace_bytes(3, huge, 1) == 0
+
+
+FAKE = 1 << 40  # never dereferenced: every call below fails validation first
+
+
+def call3d(lib, image=FAKE, mask=FAKE + (1 << 30), spacing=(1.0, 1.0, 1.0), v=1e10, lam=1.0, it=2,
+           out=FAKE + (2 << 30), C=1, D=8, H=8, W=8, ws=FAKE + (3 << 30), wsb=1 << 20):
+    sp = (ctypes.c_float * 3)(*spacing) if spacing is not None else None
+    return lib.ggdt3d(ctypes.c_void_p(image) if image else None, ctypes.c_void_p(mask) if mask else None, sp, v, lam,
+                      it, ctypes.c_void_p(out) if out else None, C, D, H, W, ctypes.c_void_p(ws) if ws else None,
+                      wsb, None)
+
+
+def test_validation_codes(lib):
+    assert call3d(lib, image=0) == -1
+    assert call3d(lib, out=0) == -1
+    assert call3d(lib, ws=0) == -1
+    assert call3d(lib, spacing=None) == -1
+    assert call3d(lib, C=0) == -2
+    assert call3d(lib, D=0) == -2
+    assert call3d(lib, C=17) == -2
+    assert call3d(lib, lam=-0.1) == -3
+    assert call3d(lib, lam=1.5) == -3
+    assert call3d(lib, lam=float("nan")) == -3
+    assert call3d(lib, v=float("inf")) == -3
+    assert call3d(lib, v=-1.0) == -3
+    assert call3d(lib, it=-1) == -3
+    assert call3d(lib, spacing=(1.0, 0.0, 1.0)) == -3
+    assert call3d(lib, spacing=(1.0, float("nan"), 1.0)) == -3
+    assert call3d(lib, wsb=16) == -4
+    assert call3d(lib, out=FAKE + 64) == -7           # out overlaps image
+    assert call3d(lib, out=FAKE + (3 << 30) + 8) == -7  # out overlaps workspace
+
+
+def test_valid_call_without_device_is_not_a_validation_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("would launch on fake pointers when a GPU is present")
+    rc = call3d(lib)
+    assert rc in (-5, -8, 0)  # no GPU here: HIP error / unsupported device
