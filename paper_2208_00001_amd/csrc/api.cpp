@@ -19,10 +19,10 @@ int g_prof_cap = 0;
 int g_prof_used = 0;
 }  // namespace
 
-hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, unsigned* flags, hipStream_t stream) {
+hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, hipStream_t stream) {
   const bool prof = g_prof_events && g_prof_used < g_prof_cap;
   if (prof) hipEventRecord(g_prof_events[2 * g_prof_used], stream);
-  const hipError_t e = launch_pass(d, ndim, words, flags, g_spin_limit, 0, stream);
+  const hipError_t e = launch_pass(d, ndim, words, g_spin_limit, stream);
   if (prof) hipEventRecord(g_prof_events[2 * g_prof_used++ + 1], stream);
   return e;
 }
@@ -93,22 +93,14 @@ int check_alias(const void* out, size_t nout, const void* const* ins, const size
   return GGDT_OK;
 }
 
-void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ, int* K) {
+void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ) {
+  (void)tu;
   if (pr.ndim == 3) {
     *TP = kTileP3;
     *TQ = kTileQ3;
-    int k = tu.chunk > 0 ? tu.chunk : kChunk3;
-    if (k > kTileP3) k = kTileP3;
-    // keep the LDS planes (2 + 2C) * (TP + 2K) * (TQ + 2K) floats within 64 KiB
-    while (k > 1 && (size_t)(2 + 2 * pr.C) * (kTileP3 + 2 * k) * (kTileQ3 + 2 * k) * 4 > 65536) --k;
-    *K = k;
   } else {
     *TP = 1;
     *TQ = kTileQ2;
-    int k = tu.chunk > 0 ? tu.chunk : kChunk2;
-    if (k > kTileQ2) k = kTileQ2;
-    while (k > 1 && (size_t)(2 + 2 * pr.C) * (kTileQ2 + 2 * k) * 4 > 65536) --k;
-    *K = k;
   }
 }
 
@@ -173,8 +165,8 @@ int requested_mode(float lam, int C) {
 }
 
 int max_tiles(const Problem& pr, const Tuning& tu) {
-  int TP, TQ, K;
-  tile_shape(pr, tu, &TP, &TQ, &K);
+  int TP, TQ;
+  tile_shape(pr, tu, &TP, &TQ);
   int best = 1;
   for (int a = 0; a < pr.ndim; ++a) {
     PassDesc d;
@@ -185,9 +177,12 @@ int max_tiles(const Problem& pr, const Tuning& tu) {
   return best;
 }
 
+// Header, then the exchange words: two parity slots of one word per tile cell.
 size_t workspace_for(const Problem& pr, const Tuning& tu) {
-  const size_t flags = ((size_t)max_tiles(pr, tu) * 4 + 255) / 256 * 256;
-  return (size_t)kHeaderWords * 4 + flags;
+  int TP, TQ;
+  tile_shape(pr, tu, &TP, &TQ);
+  const size_t xbuf = ((size_t)2 * max_tiles(pr, tu) * TP * TQ * 8 + 255) / 256 * 256;
+  return (size_t)kHeaderWords * 4 + xbuf;
 }
 
 // Enqueue the whole forward schedule of one instance.
@@ -195,9 +190,9 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
                     hipStream_t stream) {
   unsigned* words = (unsigned*)ws;
-  unsigned* flags = words + kHeaderWords;
-  const int nflag_words = (int)((workspace_for(pr, tu) - kHeaderWords * 4) / 4);
-  if (launch_reset(words, kHeaderWords + nflag_words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  unsigned long long* xbuf = (unsigned long long*)(words + kHeaderWords);
+  const long long nwords = (long long)(workspace_for(pr, tu) / 4);
+  if (launch_reset(words, nwords, stream) != hipSuccess) return GGDT_ERR_HIP;
   if (iterations == 0) {
     if (launch_scale(mask, v, out, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
     return GGDT_OK;
@@ -206,8 +201,8 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
   if (mode != kModeGeneral) {
     if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   }
-  int TP, TQ, K;
-  tile_shape(pr, tu, &TP, &TQ, &K);
+  int TP, TQ;
+  tile_shape(pr, tu, &TP, &TQ);
   unsigned base = 0;
   int p = 0;
   for (int it = 0; it < iterations; ++it) {
@@ -216,9 +211,12 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
       memset(&d, 0, sizeof d);
       pass_geometry(pr, a, &d);
       edge_constants(pr, a, spacing, lam, d.A, d.W0);
+      const int K = pass_chunk_for(pr.ndim, pr.C, d.sa == 1);
+      if (K <= 0) return GGDT_ERR_UNSUPPORTED;
       d.image = image;
       d.mask = mask;
       d.D = out;
+      d.xbuf = xbuf;
       d.N = (int)pr.N;
       d.C = pr.C;
       d.TP = TP;
@@ -234,9 +232,9 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
         d.sign = s == 0 ? 1 : -1;
         d.init = p == 0 ? 1 : 0;
         d.rec = records ? records + (size_t)p * pr.N : nullptr;
-        d.flag_base = base;
+        d.epoch_base = base;
         base += (unsigned)d.nchunk + 1u;
-        if (launch_pass_profiled(d, pr.ndim, words, flags, stream) != hipSuccess) return GGDT_ERR_HIP;
+        if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
       }
     }
   }

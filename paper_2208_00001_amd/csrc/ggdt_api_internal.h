@@ -12,8 +12,8 @@ namespace ggdt {
 
 constexpr int kMaxChannels = 16;
 constexpr unsigned long long kDefaultSpinLimit = 1ull << 21;
-constexpr int kTileP3 = 16, kTileQ3 = 16, kChunk3 = 8;  // 3D plane tile and chunk
-constexpr int kTileQ2 = 256, kChunk2 = 32;              // 2D row tile and chunk
+constexpr int kTileP3 = 16, kTileQ3 = 16;  // 3D plane tile
+constexpr int kTileQ2 = 256;              // 2D row tile
 
 extern unsigned long long g_spin_limit;
 
@@ -33,12 +33,12 @@ struct Tuning {
 
 const char* status_text(int status);
 // Launch a pass kernel, recording profiling events around it when profiling is on.
-hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, unsigned* flags, hipStream_t stream);
+hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, hipStream_t stream);
 int check_device();
 int make_problem(int ndim, const int* dims, int C, Problem* pr);
 int check_params(int ndim, const float* spacing, float v, float lam, int iterations);
 int check_alias(const void* out, size_t nout, const void* const* ins, const size_t* nins, int nin);
-void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ, int* K);
+void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ);
 void pass_geometry(const Problem& pr, int axis, PassDesc* d);
 void edge_constants(const Problem& pr, int axis, const float* spacing, float lam, float* A, float* W0);
 int requested_mode(float lam, int C);

@@ -2,17 +2,21 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace ggdt {
 
-// Workspace layout: a 256-byte header of 32-bit words, then one progress word per
-// tile (rounded up to 256 bytes).
+// Workspace layout: a 256-byte header of 32-bit words, then the tile exchange
+// area (see PassDesc::xbuf), 256-byte aligned.
 constexpr int kHeaderWords = 64;
 constexpr int kWordAbort = 0;   // non-zero once a bounded wait expired (watchdog)
 constexpr int kWordClass = 1;   // image classification bits, see below
 constexpr unsigned kClassTiny = 1u;  // some image value with 0 < |I| < 2^-40
 constexpr unsigned kClassHuge = 2u;  // some image value with |I| > 2^60 or not finite
+
+constexpr int kThreads = 256;         // threads per pass workgroup
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Edge-cost evaluation modes.  The fast modes give the same bits as the general
 // formula whenever the classification word allows them (checked on the device).
@@ -20,6 +24,24 @@ enum Mode : int {
   kModeLam0 = 0,     // lambda == 0: w = sqrtf(A_j), a per-offset constant
   kModeLam1C1 = 1,   // lambda == 1 and C == 1: w = |I(x) - I(y)|
   kModeGeneral = 2,  // w = sqrtf(fmaf(lambda, g, A_j))
+};
+
+// LDS layout of the pass kernel for one tile geometry.  A chunk stages K + 1
+// planes (scan positions t0-1 .. t0+K-1) of the image and of D_old on the tile's
+// box (tile grown by K on each plane axis).  When the scan axis is the
+// contiguous memory axis, staged planes are stored cell-major (one run of
+// scan positions per cell) so that the global->LDS copies read contiguous runs.
+template <int NDIM, int TP, int TQ, int K, bool SCANC>
+struct Layout {
+  static constexpr int BQ = TQ + 2 * K;
+  static constexpr int BP = NDIM == 3 ? TP + 2 * K : 1;
+  static constexpr int NB = BP * BQ;               // cells of a box plane
+  static constexpr int P = K + 1;                   // staged planes per chunk
+  static constexpr int SC = (P % 2 == 0) ? P + 1 : P;  // odd per-cell stride (cell-major layout)
+  static constexpr int SCR = (K % 2 == 0) ? K + 1 : K; // odd per-cell stride of staged results
+  static constexpr int STAGE = SCANC ? NB * SC : NB * P;  // floats of one staged array
+  static constexpr int RES = SCANC ? TP * TQ * SCR : 0;   // floats of the staged results
+  static constexpr size_t bytes(int C) { return sizeof(float) * (size_t)(2 * NB + STAGE * (1 + C) + RES); }
 };
 
 // Geometry and parameters of one directional pass over one instance.  The pass
@@ -32,13 +54,13 @@ struct PassDesc {
   const float* mask;   // (N), read when init != 0
   float* D;            // (N), in/out
   uint8_t* rec;        // (N) records of this pass, or nullptr
+  unsigned long long* xbuf;  // exchange words [2][ntp * ntq][TP * TQ]
   int N;               // voxels per channel
   int sa, sp, sq;      // element strides of the scan axis and of p, q
   int Na, Np, Nq;
   int sign;
   int C;
-  int TP, TQ;          // plane tile (must match the kernel instantiation)
-  int K;               // scan steps per chunk (1 <= K <= min(TP (3D), TQ))
+  int TP, TQ, K;       // plane tile and chunk length (select the kernel instantiation)
   int ntp, ntq;        // tiles along p and q
   int nchunk;          // ceil((Na - 1) / K)
   int init;            // D_old := v * M (first pass of a schedule)
@@ -46,21 +68,19 @@ struct PassDesc {
   float v, lam;
   float A[9];          // (float)((1 - lambda) * |dx|_s^2) per offset j
   float W0[9];         // sqrtf(A[j]), used when lambda == 0
-  unsigned flag_base;  // progress words of this pass count up from flag_base
+  unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
 };
 
-// Launch one directional pass.  `words` is the workspace header, `flags` the
-// per-tile progress words (at least ntp * ntq).  Returns a hipError_t.
-hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned* flags,
-                       unsigned long long spin_limit, int grid_cap, hipStream_t stream);
+// Pick the chunk length for a tile geometry so that the kernel's LDS fits.
+// Returns 0 if no instantiation fits (too many channels).
+int pass_chunk_for(int ndim, int C, bool scan_contiguous);
 
-// Largest grid of co-resident workgroups for the pass kernel that `d` selects.
-int pass_grid_capacity(const PassDesc& d, int ndim);
+// Launch one directional pass.  `words` is the workspace header.  Returns a
+// hipError_t (hipErrorInvalidConfiguration if no kernel fits).
+hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
+                       hipStream_t stream);
 
-// LDS bytes the pass kernel needs for this geometry.
-size_t pass_lds_bytes(const PassDesc& d, int ndim);
-
-hipError_t launch_reset(unsigned* ws, int nwords, hipStream_t stream);
+hipError_t launch_reset(unsigned* ws, long long nwords, hipStream_t stream);
 hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream);
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream);
 
