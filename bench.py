@@ -6,6 +6,13 @@ A step is one whole forward transform of the 3D workload: a 256^3 fp32 volume
 voxel-updates/s = voxels x directional passes x iterations / time.
 
 Also reported (same JSON line):
+  batched       64 ragged 2D/3D instances (48 volumes U[64,192]x U[64,192] x U[64,96],
+                16 images U[256,1024]^2, lambda U[0,1], spacing U[0.5,3], 2-4 iterations)
+                in one autotuned persistent launch replayed from a HIP graph, vs
+                the same instances as 64 plain per-instance calls on one stream
+  backward      4 x 128^3 volumes, lambda 0.7, soft mask, 3 iterations: batched
+                forward-with-records + batched backward (one launch each) vs
+                per-volume forward-with-records + backward launches
   roofline      the directional-pass kernel's algorithmic bytes (12 B per voxel
                 update: read I(x), read D_old(x), write D(x)) per launch over its
                 average launch duration, timed with HIP events on its stream,
@@ -66,12 +73,104 @@ def cpu_baseline(c):
             "sample": f"1 iteration (6 passes) of the {c['name']} volume, {vu} voxel-updates in {dt:.1f} s"}
 
 
+def _time(fn, reps):
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_batched(reps):
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd import synth, tune
+    from paper_2208_00001_amd.batched import BatchedPlan
+
+    dev = "cuda:0"
+    cases = synth.config4()
+    inst = [dict(image=torch.from_numpy(c["image"]).to(dev), softmask=torch.from_numpy(c["mask"]).to(dev),
+                 spacing=c["spacing"], v=c["v"], lam=c["lam"], iterations=c["iterations"]) for c in cases]
+    vu = sum(int(np.prod(c["mask"].shape)) * 2 * c["mask"].ndim * c["iterations"] for c in cases)
+    best = tune.tune(inst, use_cache=False)
+    plan = BatchedPlan(inst, best["tuning"])
+    plan.capture()
+    plan.replay()
+    ms_b = _time(plan.replay, reps)
+    assert plan.status() == 0, "watchdog fired (batched)"
+    outs = [torch.empty_like(d["softmask"]) for d in inst]
+    wss = [B.new_workspace(tuple(d["softmask"].shape), 1, dev) for d in inst]
+
+    def plain():
+        for d, c, o, w in zip(inst, cases, outs, wss):
+            fn = B.ggdt3d if c["mask"].ndim == 3 else B.ggdt2d
+            fn(d["image"], d["softmask"], c["spacing"], c["v"], c["lam"], c["iterations"], out=o, workspace=w)
+
+    plain()
+    ms_p = _time(plain, reps)
+    same = all(torch.equal(o, b) for o, b in zip(outs, plan.outputs))
+    plan.close()
+    return {"workload": "64 ragged instances (48 3D + 16 2D), lambda U[0,1], 2-4 iterations",
+            "voxel_updates": vu, "batched_ms": ms_b, "plain_ms": ms_p, "speedup": ms_p / ms_b,
+            "batched_value": vu / (ms_b * 1e-3), "plain_value": vu / (ms_p * 1e-3), "unit": "voxel-updates/s",
+            "tuning": best["tuning"], "tuning_trials": best["trials"], "outputs_identical": same}
+
+
+def bench_backward(reps):
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd import synth
+    from paper_2208_00001_amd.batched import BatchedPlan
+
+    dev = "cuda:0"
+    cases = synth.config5()
+    inst = [dict(image=torch.from_numpy(c["image"]).to(dev), softmask=torch.from_numpy(c["mask"]).to(dev),
+                 spacing=c["spacing"], v=c["v"], lam=c["lam"], iterations=c["iterations"], records=True,
+                 grad_out=torch.from_numpy(c["weight"]).to(dev)) for c in cases]
+    vu = sum(int(np.prod(c["mask"].shape)) * 6 * c["iterations"] for c in cases)
+    plan = BatchedPlan(inst)
+
+    def batched():
+        plan.run()
+        plan.backward()
+
+    def plain():
+        for d, c in zip(inst, cases):
+            out, rec = B.ggdt_forward_rec(d["image"], d["softmask"], c["spacing"], c["v"], c["lam"], c["iterations"])
+            B.ggdt_backward(d["image"], rec, d["grad_out"], c["spacing"], c["v"], c["lam"], c["iterations"])
+
+    batched()
+    plain()
+    ms_b = _time(batched, reps)
+    ms_p = _time(plain, reps)
+    ms_bf = _time(plan.run, reps)
+    ms_bb = _time(plan.backward, reps)
+    assert plan.status() == 0, "watchdog fired (backward)"
+    plan.close()
+    return {"workload": "4 x 128^3, lambda 0.7, soft mask, v 10, 3 iterations, L = sum(W * D)",
+            "voxel_updates_forward": vu, "batched_fwd_bwd_ms": ms_b, "plain_fwd_bwd_ms": ms_p,
+            "speedup": ms_p / ms_b, "batched_forward_ms": ms_bf, "batched_backward_ms": ms_bb,
+            "unit": "ms per forward+backward"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched and backward comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this path has no multi-GPU mode (asked for --gpus {args.gpus})",
@@ -147,6 +246,9 @@ def main():
                      "kernel": "directional pass (3D, lambda=1 C=1 path)", "bytes_per_voxel_update": BYTES_PER_VU,
                      "launches_timed": len(durs), "avg_launch_ms": avg_ms},
     }
+    if not args.no_batched:
+        line["batched"] = bench_batched(max(3, min(args.steps, 10)))
+        line["backward"] = bench_backward(max(3, min(args.steps, 10)))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(line), flush=True)

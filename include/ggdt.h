@@ -103,12 +103,18 @@ int ggdt3d_forward_rec(const float* image, const float* softmask, const float* s
                        float lambda, int iterations, float* out, uint8_t* records, int C, int D, int H,
                        int W, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Bytes of device workspace the backward entry points need: the forward's
+ * workspace plus one fp32 adjoint buffer of prod(dims) values.  0 for invalid
+ * shapes.  1 <= C <= 8 for the backward. */
+size_t ggdt_backward_workspace_bytes(int ndim, const int* dims, int C);
+
 /* Backward: exact reverse of the recorded schedule.  Given dL/dD (grad_out) and
  * the records of the forward with the same image, spacing, v, lambda and
  * iterations, writes dL/dI (grad_image, shape of image) and dL/dM (grad_softmask,
- * shape of softmask).  Where w = 0 the derivative of w is taken as 0.
- * grad_softmask doubles as the adjoint accumulator; outputs must not overlap the
- * inputs or each other. */
+ * shape of softmask).  Where w = 0 the derivative of w is taken as 0.  The
+ * adjoint is carried pass by pass in grad_softmask and the workspace's adjoint
+ * buffer; outputs must not overlap the inputs or each other.  Records from a
+ * different schedule give unspecified gradients (never out-of-bounds accesses). */
 int ggdt2d_backward(const float* image, const uint8_t* records, const float* grad_out,
                     const float* spacing, float v, float lambda, int iterations, float* grad_image,
                     float* grad_softmask, int C, int H, int W, void* workspace, size_t workspace_bytes,
@@ -188,6 +194,11 @@ int ggdt_batched_run(const ggdt_plan* plan, void* workspace, size_t workspace_by
  * records, grad_out, grad_image and grad_softmask). */
 int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
+
+/* Shape of a plan, for diagnostics and tuning reports (any pointer may be NULL):
+ * instances, forward grid, backward grid (0 if the plan has no backward),
+ * dynamic LDS bytes of the forward and backward launches. */
+int ggdt_plan_info(const ggdt_plan* plan, int* n, int* grid, int* bwd_grid, size_t* lds, size_t* bwd_lds);
 
 void ggdt_plan_destroy(ggdt_plan* plan);
 

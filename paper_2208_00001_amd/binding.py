@@ -45,6 +45,7 @@ _SIGS = {
     "ggdt_strerror": (ctypes.c_char_p, [_c_int]),
     "ggdt_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt_records_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt_backward_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt2d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp, _c_size, _vp]),
     "ggdt3d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int, _vp, _c_size,
                         _vp]),
@@ -64,6 +65,7 @@ _SIGS = {
     "ggdt_batched_run": (_c_int, [_vp, _vp, _c_size, _vp]),
     "ggdt_batched_backward": (_c_int, [_vp, _vp, _c_size, _vp]),
     "ggdt_plan_destroy": (None, [_vp]),
+    "ggdt_plan_info": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 
@@ -190,7 +192,10 @@ def ggdt_backward(image, records, grad_out, spacing, v, lamb, iterations, worksp
     gi = torch.empty_like(image)
     gm = torch.empty(spatial, dtype=torch.float32, device=image.device)
     if workspace is None:
-        workspace = new_workspace(spatial, C, image.device)
+        n = int(lib.ggdt_backward_workspace_bytes(nd, _dims(spatial), C))
+        if n == 0:
+            raise ValueError(f"invalid shape {spatial} with C={C} for the backward")
+        workspace = torch.empty(n, dtype=torch.uint8, device=image.device)
     fn = lib.ggdt2d_backward if nd == 2 else lib.ggdt3d_backward
     rc = fn(_ptr(image), _ptr(records.contiguous()), _ptr(grad_out), _spacing(spacing, nd), float(v), float(lamb),
             int(iterations), _ptr(gi), _ptr(gm), C, *spatial, _ptr(workspace), workspace.numel(), _stream())

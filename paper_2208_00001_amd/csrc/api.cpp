@@ -19,11 +19,24 @@ int g_prof_cap = 0;
 int g_prof_used = 0;
 }  // namespace
 
+namespace {
+bool g_prof_open = false;
+}
+
+void prof_before(hipStream_t stream) {
+  g_prof_open = g_prof_events && g_prof_used < g_prof_cap;
+  if (g_prof_open) (void)hipEventRecord(g_prof_events[2 * g_prof_used], stream);
+}
+
+void prof_after(hipStream_t stream) {
+  if (g_prof_open) (void)hipEventRecord(g_prof_events[2 * g_prof_used++ + 1], stream);
+  g_prof_open = false;
+}
+
 hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, hipStream_t stream) {
-  const bool prof = g_prof_events && g_prof_used < g_prof_cap;
-  if (prof) hipEventRecord(g_prof_events[2 * g_prof_used], stream);
+  prof_before(stream);
   const hipError_t e = launch_pass(d, ndim, words, g_spin_limit, stream);
-  if (prof) hipEventRecord(g_prof_events[2 * g_prof_used++ + 1], stream);
+  prof_after(stream);
   return e;
 }
 
@@ -201,43 +214,49 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
   if (mode != kModeGeneral) {
     if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   }
-  int TP, TQ;
-  tile_shape(pr, tu, &TP, &TQ);
   unsigned base = 0;
-  int p = 0;
-  for (int it = 0; it < iterations; ++it) {
-    for (int a = 0; a < pr.ndim; ++a) {
-      PassDesc d;
-      memset(&d, 0, sizeof d);
-      pass_geometry(pr, a, &d);
-      edge_constants(pr, a, spacing, lam, d.A, d.W0);
-      const int K = pass_chunk_for(pr.ndim, pr.C, d.sa == 1);
-      if (K <= 0) return GGDT_ERR_UNSUPPORTED;
-      d.image = image;
-      d.mask = mask;
-      d.D = out;
-      d.xbuf = xbuf;
-      d.N = (int)pr.N;
-      d.C = pr.C;
-      d.TP = TP;
-      d.TQ = TQ;
-      d.K = K;
-      d.ntp = (d.Np + TP - 1) / TP;
-      d.ntq = (d.Nq + TQ - 1) / TQ;
-      d.nchunk = (d.Na - 1 + K - 1) / K;
-      d.mode = mode;
-      d.v = v;
-      d.lam = lam;
-      for (int s = 0; s < 2; ++s, ++p) {
-        d.sign = s == 0 ? 1 : -1;
-        d.init = p == 0 ? 1 : 0;
-        d.rec = records ? records + (size_t)p * pr.N : nullptr;
-        d.epoch_base = base;
-        base += (unsigned)d.nchunk + 1u;
-        if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
-      }
-    }
+  const int npass = iterations * 2 * pr.ndim;
+  for (int p = 0; p < npass; ++p) {
+    PassDesc d;
+    const int rc = build_pass(pr, image, mask, spacing, v, lam, out, records, p, base, &d);
+    if (rc) return rc;
+    d.xbuf = xbuf;
+    base += (unsigned)d.nchunk + 1u;
+    if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   }
+  (void)tu;
+  return GGDT_OK;
+}
+
+int build_pass(const Problem& pr, const float* image, const float* mask, const float* spacing, float v, float lam,
+               float* out, uint8_t* records, int p, unsigned epoch_base, PassDesc* d) {
+  const int a = (p % (2 * pr.ndim)) / 2;
+  const int TP = pr.ndim == 3 ? kTileP3 : 1;
+  const int TQ = pr.ndim == 3 ? kTileQ3 : kTileQ2;
+  memset(d, 0, sizeof *d);
+  pass_geometry(pr, a, d);
+  edge_constants(pr, a, spacing, lam, d->A, d->W0);
+  const int K = pass_chunk_for(pr.ndim, pr.C, d->sa == 1);
+  if (K <= 0) return GGDT_ERR_UNSUPPORTED;
+  d->image = image;
+  d->mask = mask;
+  d->D = out;
+  d->xbuf = nullptr;
+  d->N = (int)pr.N;
+  d->C = pr.C;
+  d->TP = TP;
+  d->TQ = TQ;
+  d->K = K;
+  d->ntp = (d->Np + TP - 1) / TP;
+  d->ntq = (d->Nq + TQ - 1) / TQ;
+  d->nchunk = (d->Na - 1 + K - 1) / K;
+  d->mode = requested_mode(lam, pr.C);
+  d->v = v;
+  d->lam = lam;
+  d->sign = (p % 2 == 0) ? 1 : -1;
+  d->init = p == 0 ? 1 : 0;
+  d->rec = records ? records + (size_t)p * pr.N : nullptr;
+  d->epoch_base = epoch_base;
   return GGDT_OK;
 }
 

@@ -1,0 +1,168 @@
+// Backward (reverse-mode) kernels: one launch per reversed pass of one instance,
+// and the batched persistent launch over many instances (see backward_device.h).
+#include "backward_device.h"
+
+namespace ggdt {
+namespace {
+
+using namespace dev;
+
+template <int NDIM, int TP, int TQ, int K, bool SCANC>
+__global__ __launch_bounds__(kThreads) void bwd_pass_kernel(BwdDesc g, unsigned* words, unsigned long long limit) {
+  extern __shared__ float lds[];
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  run_bwd_pass_mode<NDIM, TP, TQ, K, SCANC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
+                                            xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+using BwdKernel = void (*)(BwdDesc, unsigned*, unsigned long long);
+
+template <int NDIM, int TP, int TQ, int K>
+BwdKernel pick_bwd(bool scanc) {
+  return scanc ? bwd_pass_kernel<NDIM, TP, TQ, K, true> : bwd_pass_kernel<NDIM, TP, TQ, K, false>;
+}
+
+BwdKernel select_bwd(const BwdDesc& d, int ndim) {
+  const bool scanc = d.sa == 1;
+  if (ndim == 3) {
+    if (d.K == 4) return pick_bwd<3, kTP3, kTQ3, 4>(scanc);
+    if (d.K == 2) return pick_bwd<3, kTP3, kTQ3, 2>(scanc);
+  } else {
+    if (d.K == 16) return pick_bwd<2, 1, kTQ2, 16>(scanc);
+    if (d.K == 8) return pick_bwd<2, 1, kTQ2, 8>(scanc);
+  }
+  return nullptr;
+}
+
+size_t bwd_lds(int ndim, int K, int C, bool scanc) {
+  if (ndim == 3) {
+    if (K == 4) return scanc ? BLayout<3, kTP3, kTQ3, 4, true>::bytes(C) : BLayout<3, kTP3, kTQ3, 4, false>::bytes(C);
+    if (K == 2) return scanc ? BLayout<3, kTP3, kTQ3, 2, true>::bytes(C) : BLayout<3, kTP3, kTQ3, 2, false>::bytes(C);
+  } else {
+    if (K == 16) return scanc ? BLayout<2, 1, kTQ2, 16, true>::bytes(C) : BLayout<2, 1, kTQ2, 16, false>::bytes(C);
+    if (K == 8) return scanc ? BLayout<2, 1, kTQ2, 8, true>::bytes(C) : BLayout<2, 1, kTQ2, 8, false>::bytes(C);
+  }
+  return 0;
+}
+
+int capacity_of(const void* fn, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+// Batched: every reversed pass of every instance, instance-local barriers in
+// between (same structure as the batched forward kernel).
+__device__ bool bwd_instance_barrier(unsigned* counter, unsigned target, unsigned* words, unsigned long long limit) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned long long polls = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (ld_relaxed(words + kWordAbort) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (++polls > limit) {
+        __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = s_ok != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+__global__ __launch_bounds__(kThreads) void batched_bwd_kernel(const BatchInst* __restrict__ insts, int ninst,
+                                                               const BwdDesc* __restrict__ passes, unsigned char* ws,
+                                                               unsigned long long limit) {
+  extern __shared__ float lds[];
+  unsigned* words = reinterpret_cast<unsigned*>(ws);
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].wg0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchInst in = insts[lo];
+  const int wg = b - in.wg0;
+  if (wg < 0 || wg >= in.nwg) return;
+  unsigned long long* xbuf = reinterpret_cast<unsigned long long*>(ws + in.xbuf_off);
+  unsigned* ctr = reinterpret_cast<unsigned*>(ws + in.ctr_off);
+  const unsigned* cls = reinterpret_cast<const unsigned*>(ws + in.cls_off);
+  for (int p = 0; p < in.npass; ++p) {
+    const BwdDesc* gp = passes + in.pass0 + p;
+    const bool scanc = gp->sa == 1;
+    bool ok;
+    if (in.ndim == 3)
+      ok = scanc ? run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, true>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
+                 : run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, false>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    else
+      ok = scanc ? run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, true>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
+                 : run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, false>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    if (!ok) return;
+    if (p + 1 < in.npass && !bwd_instance_barrier(ctr, (unsigned)(p + 1) * (unsigned)in.nwg, words, limit)) return;
+  }
+}
+
+}  // namespace
+
+int bwd_chunk_for(int ndim, int C, bool scan_contiguous) {
+  const int ks3[2] = {4, 2}, ks2[2] = {16, 8};
+  for (int i = 0; i < 2; ++i) {
+    const int K = ndim == 3 ? ks3[i] : ks2[i];
+    if (bwd_lds(ndim, K, C, scan_contiguous) <= kMaxLdsBytes) return K;
+  }
+  return 0;
+}
+
+hipError_t launch_bwd_pass(const BwdDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
+                           hipStream_t stream) {
+  BwdKernel fn = select_bwd(d, ndim);
+  if (!fn) return hipErrorInvalidConfiguration;
+  const size_t lds = bwd_lds(ndim, d.K, d.C, d.sa == 1);
+  if (lds == 0 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+  const int cap = capacity_of((const void*)fn, lds);
+  if (cap <= 0) return hipErrorInvalidConfiguration;
+  const int ntiles = d.ntp * d.ntq;
+  const int grid = ntiles < cap ? ntiles : cap;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, stream, d, words, spin_limit);
+  return hipGetLastError();
+}
+
+size_t batched_bwd_lds_bytes(int C, bool has2d, bool has3d) {
+  size_t b = 0;
+  if (has3d) {
+    b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, true>::bytes(C));
+    b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, false>::bytes(C));
+  }
+  if (has2d) {
+    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, true>::bytes(C));
+    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, false>::bytes(C));
+  }
+  return b;
+}
+
+int batched_bwd_capacity(size_t lds) { return capacity_of((const void*)batched_bwd_kernel, lds); }
+
+hipError_t launch_batched_bwd(const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws, int grid,
+                              size_t lds, unsigned long long spin_limit, hipStream_t stream) {
+  hipLaunchKernelGGL(batched_bwd_kernel, dim3(grid), dim3(kThreads), lds, stream, insts, ninst, passes, ws,
+                     spin_limit);
+  return hipGetLastError();
+}
+
+}  // namespace ggdt

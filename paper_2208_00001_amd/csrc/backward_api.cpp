@@ -1,0 +1,142 @@
+// C ABI of the backward (single instance: one launch per reversed pass;
+// batched: one persistent launch, tables built by ggdt_batched_plan).
+#include <math.h>
+#include <string.h>
+
+#include "ggdt.h"
+#include "ggdt_api_internal.h"
+#include "ggdt_internal.h"
+
+namespace ggdt {
+
+constexpr int kMaxBwdChannels = 8;
+
+size_t bwd_workspace_for(const Problem& pr) {
+  const size_t base = workspace_for(pr, Tuning{});
+  return base + ((size_t)pr.N * 4 + 255) / 256 * 256;
+}
+
+// Descriptor of the reverse of forward pass p; a_in / a_out / xbuf set by the caller.
+int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,
+                   float* gI, int p, int K, unsigned epoch_base, BwdDesc* d) {
+  PassDesc f;
+  const int rc = build_pass(pr, image, nullptr, spacing, 1.0f, lam, nullptr, nullptr, p, 0, &f);
+  if (rc) return rc;
+  memset(d, 0, sizeof *d);
+  d->image = image;
+  d->rec = records + (size_t)p * pr.N;
+  d->gI = gI;
+  d->N = (int)pr.N;
+  d->sa = f.sa;
+  d->sp = f.sp;
+  d->sq = f.sq;
+  d->Na = f.Na;
+  d->Np = f.Np;
+  d->Nq = f.Nq;
+  d->sign = f.sign;
+  d->C = pr.C;
+  d->TP = f.TP;
+  d->TQ = f.TQ;
+  d->K = K;
+  d->ntp = f.ntp;
+  d->ntq = f.ntq;
+  d->nchunk = (f.Na - 1 + K - 1) / K;
+  d->mode = f.mode;
+  d->lam = lam;
+  for (int j = 0; j < 9; ++j) d->A[j] = f.A[j];
+  d->epoch_base = epoch_base;
+  d->a_in_off = -1;
+  d->a_out_off = -1;
+  return GGDT_OK;
+}
+
+namespace {
+
+int backward_entry(int ndim, const int* dims, int C, const float* image, const uint8_t* records,
+                   const float* grad_out, const float* spacing, float v, float lam, int iterations, float* grad_image,
+                   float* grad_softmask, void* ws, size_t wsb, hipStream_t stream) {
+  if (!image || !records || !grad_out || !grad_image || !grad_softmask || !ws || !dims) return GGDT_ERR_NULL_PTR;
+  Problem pr;
+  int rc = make_problem(ndim, dims, C, &pr);
+  if (rc) return rc;
+  if (C > kMaxBwdChannels) return GGDT_ERR_BAD_SHAPE;
+  rc = check_params(ndim, spacing, v, lam, iterations);
+  if (rc) return rc;
+  if (wsb < bwd_workspace_for(pr)) return GGDT_ERR_WORKSPACE_TOO_SMALL;
+  const size_t nb = (size_t)pr.N * 4, ni = nb * C, nrec = (size_t)iterations * 2 * ndim * pr.N;
+  {
+    const void* ins[5] = {image, records, grad_out, ws, grad_softmask};
+    const size_t nins[5] = {ni, nrec, nb, wsb, nb};
+    if ((rc = check_alias(grad_image, ni, ins, nins, 5))) return rc;
+    const void* ins2[4] = {image, records, grad_out, ws};
+    const size_t nins2[4] = {ni, nrec, nb, wsb};
+    if ((rc = check_alias(grad_softmask, nb, ins2, nins2, 4))) return rc;
+  }
+  if ((rc = check_device())) return rc;
+  unsigned* words = (unsigned*)ws;
+  const size_t fwd_ws = workspace_for(pr, Tuning{});
+  unsigned long long* xbuf = (unsigned long long*)(words + kHeaderWords);
+  float* scratch = (float*)((unsigned char*)ws + fwd_ws);
+  if (launch_reset(words, (long long)(fwd_ws / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (launch_reset((unsigned*)grad_image, (long long)pr.N * C, stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (iterations == 0) return launch_scale(grad_out, v, grad_softmask, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
+  if (requested_mode(lam, C) == kModeLam1C1 &&
+      launch_classify(image, (long long)C * pr.N, words, stream) != hipSuccess)
+    return GGDT_ERR_HIP;
+  const int P = iterations * 2 * ndim;
+  unsigned base = 0;
+  const float* a_in = grad_out;
+  for (int q = 0; q < P; ++q) {
+    const int p = P - 1 - q;
+    BwdDesc d;
+    PassDesc g;
+    pass_geometry(pr, (p % (2 * ndim)) / 2, &g);
+    const int K = bwd_chunk_for(ndim, C, g.sa == 1);
+    if (K <= 0) return GGDT_ERR_UNSUPPORTED;
+    if ((rc = build_bwd_pass(pr, image, records, spacing, lam, grad_image, p, K, base, &d))) return rc;
+    float* a_out = ((P - 1 - q) % 2 == 0) ? grad_softmask : scratch;
+    d.a_in = a_in;
+    d.a_out = a_out;
+    d.xbuf = xbuf;
+    base += (unsigned)d.nchunk + 1u;
+    prof_before(stream);
+    const hipError_t e = launch_bwd_pass(d, ndim, words, g_spin_limit, stream);
+    prof_after(stream);
+    if (e != hipSuccess) return GGDT_ERR_HIP;
+    a_in = a_out;
+  }
+  // the last reversed pass wrote grad_softmask: dL/dM = v * abar
+  return launch_scale(grad_softmask, v, grad_softmask, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
+}
+
+}  // namespace
+}  // namespace ggdt
+
+using namespace ggdt;
+
+extern "C" {
+
+size_t ggdt_backward_workspace_bytes(int ndim, const int* dims, int C) {
+  if (!dims) return 0;
+  Problem pr;
+  if (make_problem(ndim, dims, C, &pr) || C > kMaxBwdChannels) return 0;
+  return bwd_workspace_for(pr);
+}
+
+int ggdt2d_backward(const float* image, const uint8_t* records, const float* grad_out, const float* spacing, float v,
+                    float lambda, int iterations, float* grad_image, float* grad_softmask, int C, int H, int W,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  const int dims[2] = {H, W};
+  return backward_entry(2, dims, C, image, records, grad_out, spacing, v, lambda, iterations, grad_image,
+                        grad_softmask, workspace, workspace_bytes, stream);
+}
+
+int ggdt3d_backward(const float* image, const uint8_t* records, const float* grad_out, const float* spacing, float v,
+                    float lambda, int iterations, float* grad_image, float* grad_softmask, int C, int D, int H, int W,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  const int dims[3] = {D, H, W};
+  return backward_entry(3, dims, C, image, records, grad_out, spacing, v, lambda, iterations, grad_image,
+                        grad_softmask, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

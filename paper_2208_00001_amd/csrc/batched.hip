@@ -1,0 +1,167 @@
+// Batched ragged GGDT: every pass of every instance in one persistent launch.
+//
+// Each instance owns a contiguous range of logical workgroups (split at plan
+// time in proportion to its work).  Its workgroups run its passes in schedule
+// order with the single-instance pass code (pass_device.h); between passes they
+// meet at an instance-local barrier (release fence, counter, bounded wait,
+// acquire fence), so instances never wait for each other.  The launch is sized to
+// the co-resident capacity, which the bounded waits require.
+#include "pass_device.h"
+
+namespace ggdt {
+namespace {
+
+using namespace dev;
+
+// All workgroups of an instance have finished the pass: arrive on the counter
+// and wait until `target` arrivals are seen.  False if the wait was abandoned.
+__device__ bool instance_barrier(unsigned* counter, unsigned target, unsigned* words, unsigned long long limit) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned long long polls = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (ld_relaxed(words + kWordAbort) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (++polls > limit) {
+        __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = s_ok != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+template <int NDIM, int TP, int TQ, int K, bool REC>
+__device__ __forceinline__ bool run_pass_rt(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
+                                            const unsigned* cls, int mode, unsigned long long limit, float* lds,
+                                            int wg, int G) {
+  const bool scanc = gp->sa == 1;
+  if (scanc) {
+    if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam0, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+    if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam1C1, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+    return run_pass_mode<NDIM, TP, TQ, K, true, kModeGeneral, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+  }
+  if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam0, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+  if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam1C1, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+  return run_pass_mode<NDIM, TP, TQ, K, false, kModeGeneral, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+}
+
+template <int K3, int K2, bool REC>
+__global__ __launch_bounds__(kThreads) void batched_kernel(const BatchInst* __restrict__ insts, int ninst,
+                                                           const PassDesc* __restrict__ passes, unsigned char* ws,
+                                                           unsigned long long limit) {
+  extern __shared__ float lds[];
+  unsigned* words = reinterpret_cast<unsigned*>(ws);
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].wg0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchInst in = insts[lo];
+  const int wg = b - in.wg0;
+  if (wg < 0 || wg >= in.nwg) return;
+  unsigned long long* xbuf = reinterpret_cast<unsigned long long*>(ws + in.xbuf_off);
+  unsigned* ctr = reinterpret_cast<unsigned*>(ws + in.ctr_off);
+  const unsigned* cls = reinterpret_cast<const unsigned*>(ws + in.cls_off);
+  for (int p = 0; p < in.npass; ++p) {
+    const PassDesc* gp = passes + in.pass0 + p;
+    bool ok;
+    if (in.ndim == 3)
+      ok = run_pass_rt<3, kTP3, kTQ3, K3, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
+    else
+      ok = run_pass_rt<2, 1, kTQ2, K2, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
+    if (!ok) return;
+    if (p + 1 < in.npass && !instance_barrier(ctr, (unsigned)(p + 1) * (unsigned)in.nwg, words, limit)) return;
+  }
+}
+
+// Classification of every instance's image into its class word (grid-stride
+// over the instances' values; one workgroup-level OR per instance per block).
+__global__ __launch_bounds__(256) void batched_classify_kernel(const BatchInst* __restrict__ insts, int ninst,
+                                                               unsigned char* ws) {
+  for (int i = 0; i < ninst; ++i) {
+    const BatchInst in = insts[i];
+    if (in.mode == kModeGeneral) continue;  // uniform
+    unsigned bits = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < in.nimg; t += stride) {
+      const float a = fabsf(in.image[t]);
+      if (!(a <= 0x1p60f)) bits |= kClassHuge;
+      else if (a != 0.0f && a < 0x1p-40f) bits |= kClassTiny;
+    }
+    const int tiny = __syncthreads_or((bits & kClassTiny) ? 1 : 0);
+    const int huge = __syncthreads_or((bits & kClassHuge) ? 1 : 0);
+    if (threadIdx.x == 0 && (tiny || huge))
+      __hip_atomic_fetch_or(reinterpret_cast<unsigned*>(ws + in.cls_off),
+                            (tiny ? kClassTiny : 0u) | (huge ? kClassHuge : 0u), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+using BatchedKernel = void (*)(const BatchInst*, int, const PassDesc*, unsigned char*, unsigned long long);
+
+BatchedKernel pick(int kclass, bool rec) {
+  if (kclass == 0) return rec ? batched_kernel<kBatchK3[0], kBatchK2[0], true> : batched_kernel<kBatchK3[0], kBatchK2[0], false>;
+  return rec ? batched_kernel<kBatchK3[1], kBatchK2[1], true> : batched_kernel<kBatchK3[1], kBatchK2[1], false>;
+}
+
+template <int K3, int K2>
+size_t lds_for(int C, bool has2d, bool has3d) {
+  size_t b = 0;
+  if (has3d) {
+    b = max(b, Layout<3, kTP3, kTQ3, K3, true>::bytes(C));
+    b = max(b, Layout<3, kTP3, kTQ3, K3, false>::bytes(C));
+  }
+  if (has2d) {
+    b = max(b, Layout<2, 1, kTQ2, K2, true>::bytes(C));
+    b = max(b, Layout<2, 1, kTQ2, K2, false>::bytes(C));
+  }
+  return b;
+}
+
+}  // namespace
+
+size_t batched_lds_bytes(int kclass, int C, bool has2d, bool has3d) {
+  return kclass == 0 ? lds_for<kBatchK3[0], kBatchK2[0]>(C, has2d, has3d)
+                     : lds_for<kBatchK3[1], kBatchK2[1]>(C, has2d, has3d);
+}
+
+int batched_capacity(int kclass, bool rec, size_t lds) {
+  BatchedKernel fn = pick(kclass, rec);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kThreads, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_batched(int kclass, bool rec, const BatchInst* insts, int ninst, const PassDesc* passes,
+                          unsigned char* ws, int grid, size_t lds, unsigned long long spin_limit, hipStream_t stream) {
+  BatchedKernel fn = pick(kclass, rec);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, stream, insts, ninst, passes, ws, spin_limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_classify(const BatchInst* insts, int ninst, unsigned char* ws, hipStream_t stream) {
+  hipLaunchKernelGGL(batched_classify_kernel, dim3(1024), dim3(256), 0, stream, insts, ninst, ws);
+  return hipGetLastError();
+}
+
+}  // namespace ggdt

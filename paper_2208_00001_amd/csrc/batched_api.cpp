@@ -1,0 +1,383 @@
+// C ABI of the batched ragged GGDT: plan (validation, workgroup split, device
+// tables), run (one persistent launch), destroy.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "ggdt.h"
+#include "ggdt_api_internal.h"
+#include "ggdt_internal.h"
+
+struct ggdt_plan {
+  int n = 0;
+  int kclass = 0;
+  bool rec = false;
+  bool any_classify = false;
+  int grid = 0;
+  size_t lds = 0;
+  size_t ws_bytes = 0;
+  ggdt::BatchInst* d_insts = nullptr;
+  ggdt::PassDesc* d_passes = nullptr;
+  std::vector<ggdt_instance> inst;
+  std::vector<ggdt::BatchInst> h_insts;
+  std::vector<int> nwg;
+  std::vector<long long> npix;
+  // backward tables (when every instance has records and gradient buffers)
+  bool has_bwd = false;
+  int bgrid = 0;
+  size_t blds = 0;
+  size_t fwd_ws = 0;
+  ggdt::BatchInst* d_binsts = nullptr;
+  ggdt::BwdDesc* d_bpasses = nullptr;
+};
+
+namespace ggdt {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Cost of an instance with w workgroups: planes advanced per workgroup, summed
+// over passes (each workgroup walks ceil(tiles / w) tiles through every plane)
+// plus a per-chunk synchronisation term.
+double instance_cost(const std::vector<PassDesc>& ps, int w) {
+  double c = 0.0;
+  for (const PassDesc& d : ps) {
+    const int tiles = d.ntp * d.ntq;
+    const int per = (tiles + w - 1) / w;
+    c += (double)(d.Na - 1) * per + 4.0 * d.nchunk;
+  }
+  return c;
+}
+
+int max_tiles_of(const std::vector<PassDesc>& ps) {
+  int m = 1;
+  for (const PassDesc& d : ps) m = d.ntp * d.ntq > m ? d.ntp * d.ntq : m;
+  return m;
+}
+
+int validate_instance(const ggdt_instance& in, Problem* pr) {
+  if (!in.image || !in.softmask || !in.out) return GGDT_ERR_NULL_PTR;
+  int rc = make_problem(in.ndim, in.dims, in.C, pr);
+  if (rc) return rc;
+  rc = check_params(in.ndim, in.spacing, in.v, in.lambda, in.iterations);
+  if (rc) return rc;
+  const size_t nb = (size_t)pr->N * 4, ni = (size_t)pr->N * pr->C * 4;
+  const void* ins[2] = {in.image, in.softmask};
+  const size_t nins[2] = {ni, nb};
+  rc = check_alias(in.out, nb, ins, nins, 2);
+  if (rc) return rc;
+  if (in.records) {
+    const size_t nrec = (size_t)in.iterations * 2 * in.ndim * pr->N;
+    const void* ins2[3] = {in.image, in.softmask, in.out};
+    const size_t nins2[3] = {ni, nb, nb};
+    rc = check_alias(in.records, nrec, ins2, nins2, 3);
+    if (rc) return rc;
+  }
+  return GGDT_OK;
+}
+
+}  // namespace
+}  // namespace ggdt
+
+using namespace ggdt;
+
+extern "C" {
+
+int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* tuning, ggdt_plan** plan_out,
+                      size_t* workspace_bytes) {
+  if (!instances || !plan_out || !workspace_bytes) return GGDT_ERR_NULL_PTR;
+  if (n < 1) return GGDT_ERR_BAD_SHAPE;
+  *plan_out = nullptr;
+  std::vector<Problem> prs(n);
+  int maxC = 1;
+  bool has2d = false, has3d = false, rec = false, any_cls = false;
+  for (int i = 0; i < n; ++i) {
+    const int rc = validate_instance(instances[i], &prs[i]);
+    if (rc) return rc;
+    maxC = instances[i].C > maxC ? instances[i].C : maxC;
+    has2d |= instances[i].ndim == 2;
+    has3d |= instances[i].ndim == 3;
+    rec |= instances[i].records != nullptr;
+    any_cls |= requested_mode(instances[i].lambda, instances[i].C) != kModeGeneral;
+  }
+  int kclass = maxC <= kBatchMaxC[0] ? 0 : 1;
+  if (tuning && tuning->chunk > 0) {
+    if (tuning->chunk == kBatchK3[1] || tuning->chunk == kBatchK2[1]) kclass = 1;
+    else if (tuning->chunk != kBatchK3[0] && tuning->chunk != kBatchK2[0]) return GGDT_ERR_BAD_PARAM;
+  }
+  if (maxC > kBatchMaxC[kclass]) return kclass == 0 ? GGDT_ERR_BAD_PARAM : GGDT_ERR_UNSUPPORTED;
+  int rc = check_device();
+  if (rc) return rc;
+  const size_t lds = batched_lds_bytes(kclass, maxC, has2d, has3d);
+  if (lds == 0 || lds > kMaxLdsBytes) return GGDT_ERR_UNSUPPORTED;
+  int cap = batched_capacity(kclass, rec, lds);
+  if (cap <= 0) return GGDT_ERR_HIP;
+  if (tuning && tuning->wg_per_cu > 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
+      return GGDT_ERR_HIP;
+    const int c2 = tuning->wg_per_cu * cus;
+    cap = c2 < cap ? c2 : cap;
+  }
+  if (n > cap) return GGDT_ERR_UNSUPPORTED;
+
+  // Pass descriptors (schedule order) per instance, chunk length of the kernel class.
+  std::vector<std::vector<PassDesc>> passes(n);
+  for (int i = 0; i < n; ++i) {
+    const ggdt_instance& in = instances[i];
+    const int npass = in.iterations * 2 * in.ndim;
+    unsigned base = 0;
+    for (int p = 0; p < npass; ++p) {
+      PassDesc d;
+      rc = build_pass(prs[i], in.image, in.softmask, in.spacing, in.v, in.lambda, in.out, in.records, p, base, &d);
+      if (rc) return rc;
+      d.K = in.ndim == 3 ? kBatchK3[kclass] : kBatchK2[kclass];
+      d.nchunk = (d.Na - 1 + d.K - 1) / d.K;
+      base += (unsigned)d.nchunk + 1u;
+      passes[i].push_back(d);
+    }
+  }
+
+  // Split the co-resident workgroups: one each, then greedily to the instance
+  // with the largest remaining cost while it has tiles left to spread.
+  std::vector<int> w(n, 1);
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) cost[i] = instance_cost(passes[i], 1);
+  int used = n;
+  while (used < cap) {
+    int best = -1;
+    for (int i = 0; i < n; ++i)
+      if (w[i] < max_tiles_of(passes[i]) && !passes[i].empty() && (best < 0 || cost[i] > cost[best])) best = i;
+    if (best < 0) break;
+    ++w[best];
+    cost[best] = instance_cost(passes[best], w[best]);
+    ++used;
+  }
+
+  // Workspace: header, class words, counters, exchange words per instance.
+  ggdt_plan* plan = new ggdt_plan();
+  plan->n = n;
+  plan->kclass = kclass;
+  plan->rec = rec;
+  plan->any_classify = any_cls;
+  plan->lds = lds;
+  plan->inst.assign(instances, instances + n);
+  size_t off = (size_t)kHeaderWords * 4;
+  const size_t cls_off = off;
+  off = align_up(off + (size_t)n * 4);
+  const size_t ctr_off = off;
+  off = align_up(off + (size_t)n * 4);
+  std::vector<PassDesc> flat;
+  int wg0 = 0;
+  for (int i = 0; i < n; ++i) {
+    const ggdt_instance& in = instances[i];
+    BatchInst bi;
+    memset(&bi, 0, sizeof bi);
+    bi.ndim = in.ndim;
+    bi.mode = requested_mode(in.lambda, in.C);
+    bi.npass = (int)passes[i].size();
+    bi.pass0 = (int)flat.size();
+    bi.wg0 = wg0;
+    bi.nwg = w[i];
+    bi.xbuf_off = (long long)off;
+    bi.ctr_off = (long long)(ctr_off + 4 * (size_t)i);
+    bi.cls_off = (long long)(cls_off + 4 * (size_t)i);
+    bi.image = in.image;
+    bi.nimg = (long long)prs[i].C * prs[i].N;
+    const int TPQ = in.ndim == 3 ? kTP3 * kTQ3 : kTQ2;
+    off = align_up(off + (size_t)2 * max_tiles_of(passes[i]) * TPQ * 8);
+    wg0 += w[i];
+    for (const PassDesc& d : passes[i]) flat.push_back(d);
+    plan->h_insts.push_back(bi);
+  }
+  plan->grid = wg0;
+  plan->nwg = w;
+  plan->fwd_ws = off;
+  for (int i = 0; i < n; ++i) plan->npix.push_back(prs[i].N);
+
+  // Backward tables: reversed passes, workgroups split for the backward kernel,
+  // one adjoint scratch buffer per instance after the forward's regions.
+  bool want_bwd = maxC <= 8;
+  for (int i = 0; i < n; ++i)
+    want_bwd = want_bwd && instances[i].records && instances[i].grad_out && instances[i].grad_image &&
+               instances[i].grad_softmask;
+  size_t boff = off;
+  if (want_bwd) {
+    const size_t blds = batched_bwd_lds_bytes(maxC, has2d, has3d);
+    int bcap = blds <= kMaxLdsBytes ? batched_bwd_capacity(blds) : 0;
+    if (tuning && tuning->wg_per_cu > 0 && bcap > 0) {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        bcap = tuning->wg_per_cu * cus < bcap ? tuning->wg_per_cu * cus : bcap;
+    }
+    if (bcap >= n) {
+      std::vector<std::vector<PassDesc>> bgeo(n);
+      std::vector<BwdDesc> bflat;
+      std::vector<BatchInst> bh;
+      std::vector<long long> scratch_off(n);
+      for (int i = 0; i < n; ++i) {
+        scratch_off[i] = (long long)boff;
+        boff = align_up(boff + (size_t)prs[i].N * 4);
+      }
+      for (int i = 0; i < n; ++i) {
+        const ggdt_instance& in = instances[i];
+        const int P = in.iterations * 2 * in.ndim;
+        const int K = in.ndim == 3 ? kBwdBatchK3 : kBwdBatchK2;
+        unsigned base = 0;
+        for (int q = 0; q < P; ++q) {
+          const int p = P - 1 - q;
+          BwdDesc d;
+          rc = build_bwd_pass(prs[i], in.image, in.records, in.spacing, in.lambda, in.grad_image, p, K, base, &d);
+          if (rc) {
+            ggdt_plan_destroy(plan);
+            return rc;
+          }
+          base += (unsigned)d.nchunk + 1u;
+          // abar_in: grad_out, then the previous reversed pass's output; outputs
+          // alternate so that the last one lands in grad_softmask.
+          const bool out_to_gm = (P - 1 - q) % 2 == 0;
+          d.a_out = out_to_gm ? in.grad_softmask : nullptr;
+          d.a_out_off = out_to_gm ? -1 : scratch_off[i];
+          if (q == 0) {
+            d.a_in = in.grad_out;
+          } else {
+            const bool prev_gm = (P - q) % 2 == 0;
+            d.a_in = prev_gm ? in.grad_softmask : nullptr;
+            d.a_in_off = prev_gm ? -1 : scratch_off[i];
+          }
+          PassDesc geo;
+          geo.Na = d.Na;
+          geo.ntp = d.ntp;
+          geo.ntq = d.ntq;
+          geo.nchunk = d.nchunk;
+          bgeo[i].push_back(geo);
+          bflat.push_back(d);
+        }
+      }
+      std::vector<int> bw(n, 1);
+      std::vector<double> bc(n);
+      for (int i = 0; i < n; ++i) bc[i] = instance_cost(bgeo[i], 1);
+      int bused = n;
+      while (bused < bcap) {
+        int best = -1;
+        for (int i = 0; i < n; ++i)
+          if (!bgeo[i].empty() && bw[i] < max_tiles_of(bgeo[i]) && (best < 0 || bc[i] > bc[best])) best = i;
+        if (best < 0) break;
+        ++bw[best];
+        bc[best] = instance_cost(bgeo[best], bw[best]);
+        ++bused;
+      }
+      int bwg0 = 0, pass0 = 0;
+      for (int i = 0; i < n; ++i) {
+        BatchInst bi = plan->h_insts[i];
+        bi.npass = (int)bgeo[i].size();
+        bi.pass0 = pass0;
+        bi.wg0 = bwg0;
+        bi.nwg = bw[i];
+        pass0 += bi.npass;
+        bwg0 += bw[i];
+        bh.push_back(bi);
+      }
+      if (hipMalloc((void**)&plan->d_binsts, sizeof(BatchInst) * n) != hipSuccess ||
+          hipMalloc((void**)&plan->d_bpasses, sizeof(BwdDesc) * (bflat.empty() ? 1 : bflat.size())) != hipSuccess ||
+          hipMemcpy(plan->d_binsts, bh.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice) != hipSuccess ||
+          (!bflat.empty() && hipMemcpy(plan->d_bpasses, bflat.data(), sizeof(BwdDesc) * bflat.size(),
+                                       hipMemcpyHostToDevice) != hipSuccess)) {
+        ggdt_plan_destroy(plan);
+        return GGDT_ERR_HIP;
+      }
+      plan->has_bwd = true;
+      plan->bgrid = bwg0;
+      plan->blds = blds;
+    }
+  }
+  plan->ws_bytes = plan->has_bwd ? boff : off;
+  if (hipMalloc((void**)&plan->d_insts, sizeof(BatchInst) * n) != hipSuccess ||
+      hipMalloc((void**)&plan->d_passes, sizeof(PassDesc) * (flat.empty() ? 1 : flat.size())) != hipSuccess) {
+    ggdt_plan_destroy(plan);
+    return GGDT_ERR_HIP;
+  }
+  if (hipMemcpy(plan->d_insts, plan->h_insts.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      (!flat.empty() &&
+       hipMemcpy(plan->d_passes, flat.data(), sizeof(PassDesc) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+    ggdt_plan_destroy(plan);
+    return GGDT_ERR_HIP;
+  }
+  *plan_out = plan;
+  *workspace_bytes = plan->ws_bytes;
+  return GGDT_OK;
+}
+
+int ggdt_batched_run(const ggdt_plan* plan, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!plan || !workspace) return GGDT_ERR_NULL_PTR;
+  if (workspace_bytes < plan->ws_bytes) return GGDT_ERR_WORKSPACE_TOO_SMALL;
+  unsigned char* ws = (unsigned char*)workspace;
+  if (launch_reset((unsigned*)ws, (long long)(plan->ws_bytes / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (plan->any_classify && launch_batched_classify(plan->d_insts, plan->n, ws, stream) != hipSuccess)
+    return GGDT_ERR_HIP;
+  // instances with zero iterations: D = v * M
+  for (const ggdt_instance& in : plan->inst) {
+    if (in.iterations == 0) {
+      long long nv = 1;
+      for (int b = 0; b < in.ndim; ++b) nv *= in.dims[b];
+      if (launch_scale(in.softmask, in.v, in.out, nv, stream) != hipSuccess) return GGDT_ERR_HIP;
+    }
+  }
+  prof_before(stream);
+  const hipError_t e = launch_batched(plan->kclass, plan->rec, plan->d_insts, plan->n, plan->d_passes, ws, plan->grid,
+                                      plan->lds, g_spin_limit, stream);
+  prof_after(stream);
+  return e == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
+}
+
+int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!plan || !workspace) return GGDT_ERR_NULL_PTR;
+  if (!plan->has_bwd) return GGDT_ERR_UNSUPPORTED;
+  if (workspace_bytes < plan->ws_bytes) return GGDT_ERR_WORKSPACE_TOO_SMALL;
+  unsigned char* ws = (unsigned char*)workspace;
+  if (launch_reset((unsigned*)ws, (long long)(plan->fwd_ws / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (plan->any_classify && launch_batched_classify(plan->d_insts, plan->n, ws, stream) != hipSuccess)
+    return GGDT_ERR_HIP;
+  for (int i = 0; i < plan->n; ++i) {
+    const ggdt_instance& in = plan->inst[i];
+    if (launch_reset((unsigned*)in.grad_image, plan->npix[i] * in.C, stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (in.iterations == 0 && launch_scale(in.grad_out, in.v, in.grad_softmask, plan->npix[i], stream) != hipSuccess)
+      return GGDT_ERR_HIP;
+  }
+  prof_before(stream);
+  const hipError_t e = launch_batched_bwd(plan->d_binsts, plan->n, plan->d_bpasses, ws, plan->bgrid, plan->blds,
+                                          g_spin_limit, stream);
+  prof_after(stream);
+  if (e != hipSuccess) return GGDT_ERR_HIP;
+  for (int i = 0; i < plan->n; ++i) {
+    const ggdt_instance& in = plan->inst[i];
+    if (in.iterations > 0 &&
+        launch_scale(in.grad_softmask, in.v, in.grad_softmask, plan->npix[i], stream) != hipSuccess)
+      return GGDT_ERR_HIP;
+  }
+  return GGDT_OK;
+}
+
+int ggdt_plan_info(const ggdt_plan* plan, int* n, int* grid, int* bwd_grid, size_t* lds, size_t* bwd_lds) {
+  if (!plan) return GGDT_ERR_NULL_PTR;
+  if (n) *n = plan->n;
+  if (grid) *grid = plan->grid;
+  if (bwd_grid) *bwd_grid = plan->has_bwd ? plan->bgrid : 0;
+  if (lds) *lds = plan->lds;
+  if (bwd_lds) *bwd_lds = plan->has_bwd ? plan->blds : 0;
+  return GGDT_OK;
+}
+
+void ggdt_plan_destroy(ggdt_plan* plan) {
+  if (!plan) return;
+  if (plan->d_insts) (void)hipFree(plan->d_insts);
+  if (plan->d_passes) (void)hipFree(plan->d_passes);
+  if (plan->d_binsts) (void)hipFree(plan->d_binsts);
+  if (plan->d_bpasses) (void)hipFree(plan->d_bpasses);
+  delete plan;
+}
+
+}  // extern "C"

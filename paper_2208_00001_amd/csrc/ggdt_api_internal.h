@@ -32,6 +32,14 @@ struct Tuning {
 };
 
 const char* status_text(int status);
+// Record the profiling event before / after a profiled kernel launch (no-ops
+// when profiling is off or its capacity is used up).
+void prof_before(hipStream_t stream);
+void prof_after(hipStream_t stream);
+// Build the pass descriptor of pass number p (0-based, schedule order) of an
+// instance; xbuf is left null.
+int build_pass(const Problem& pr, const float* image, const float* mask, const float* spacing, float v, float lam,
+               float* out, uint8_t* records, int p, unsigned epoch_base, PassDesc* d);
 // Launch a pass kernel, recording profiling events around it when profiling is on.
 hipError_t launch_pass_profiled(const PassDesc& d, int ndim, unsigned* words, hipStream_t stream);
 int check_device();
@@ -43,6 +51,8 @@ void pass_geometry(const Problem& pr, int axis, PassDesc* d);
 void edge_constants(const Problem& pr, int axis, const float* spacing, float lam, float* A, float* W0);
 int requested_mode(float lam, int C);
 int max_tiles(const Problem& pr, const Tuning& tu);
+int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,
+                   float* gI, int p, int K, unsigned epoch_base, BwdDesc* d);
 size_t workspace_for(const Problem& pr, const Tuning& tu);
 
 }  // namespace ggdt

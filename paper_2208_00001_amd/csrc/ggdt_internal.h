@@ -16,7 +16,7 @@ constexpr unsigned kClassTiny = 1u;  // some image value with 0 < |I| < 2^-40
 constexpr unsigned kClassHuge = 2u;  // some image value with |I| > 2^60 or not finite
 
 constexpr int kThreads = 256;         // threads per pass workgroup
-constexpr size_t kMaxLdsBytes = 160 * 1024;
+constexpr size_t kMaxLdsBytes = 159 * 1024;  // 160 KiB per CU, less room for static LDS
 
 // Edge-cost evaluation modes.  The fast modes give the same bits as the general
 // formula whenever the classification word allows them (checked on the device).
@@ -29,19 +29,21 @@ enum Mode : int {
 // LDS layout of the pass kernel for one tile geometry.  A chunk stages K + 1
 // planes (scan positions t0-1 .. t0+K-1) of the image and of D_old on the tile's
 // box (tile grown by K on each plane axis).  When the scan axis is the
-// contiguous memory axis, staged planes are stored cell-major (one run of
-// scan positions per cell) so that the global->LDS copies read contiguous runs.
+// contiguous memory axis, staged planes are stored cell-major: each cell holds a
+// run of SC consecutive memory positions along the scan axis, starting at a
+// multiple of 4, so that 16-byte global->LDS copies read aligned groups.
 template <int NDIM, int TP, int TQ, int K, bool SCANC>
 struct Layout {
   static constexpr int BQ = TQ + 2 * K;
   static constexpr int BP = NDIM == 3 ? TP + 2 * K : 1;
   static constexpr int NB = BP * BQ;               // cells of a box plane
   static constexpr int P = K + 1;                   // staged planes per chunk
-  static constexpr int SC = (P % 2 == 0) ? P + 1 : P;  // odd per-cell stride (cell-major layout)
+  static constexpr int SC = 4 * ((K + 4 + 3) / 4);  // cell-major run: K + 1 planes + up to 3 alignment slots
   static constexpr int SCR = (K % 2 == 0) ? K + 1 : K; // odd per-cell stride of staged results
   static constexpr int STAGE = SCANC ? NB * SC : NB * P;  // floats of one staged array
   static constexpr int RES = SCANC ? TP * TQ * SCR : 0;   // floats of the staged results
-  static constexpr size_t bytes(int C) { return sizeof(float) * (size_t)(2 * NB + STAGE * (1 + C) + RES); }
+  // two (D, I) pair planes, the staged D_old and image arrays, the staged results
+  static constexpr size_t bytes(int C) { return sizeof(float) * (size_t)(4 * NB + STAGE * (1 + C) + RES); }
 };
 
 // Geometry and parameters of one directional pass over one instance.  The pass
@@ -70,6 +72,73 @@ struct PassDesc {
   float W0[9];         // sqrtf(A[j]), used when lambda == 0
   unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
 };
+
+// Reverse of one forward pass (see backward_device.h).  Geometry fields as in
+// PassDesc; abar is read from a_in and written to a_out; gI accumulates dL/dI.
+struct BwdDesc {
+  const float* image;   // (C, N)
+  const uint8_t* rec;   // records of the forward pass (N)
+  const float* a_in;    // (N)
+  float* a_out;         // (N)
+  float* gI;            // (C, N)
+  unsigned long long* xbuf;
+  int N;
+  int sa, sp, sq;
+  int Na, Np, Nq;
+  int sign;
+  int C;
+  int TP, TQ, K;
+  int ntp, ntq;
+  int nchunk;           // ceil((Na - 1) / K)
+  int mode;
+  float lam;
+  float A[9];
+  unsigned epoch_base;
+  long long a_in_off;   // >= 0: a_in is at this byte offset of the workspace (batched scratch)
+  long long a_out_off;  // >= 0: same for a_out
+};
+
+// One instance of a batched launch (device-resident table).  Its passes are
+// entries [pass0, pass0 + npass) of the pass table; it runs on logical
+// workgroups [wg0, wg0 + nwg).  Offsets are in bytes from the workspace base.
+struct BatchInst {
+  int ndim;
+  int mode;            // requested Mode
+  int npass;
+  int pass0;
+  int wg0, nwg;
+  long long xbuf_off;  // exchange words of this instance
+  long long ctr_off;   // pass-barrier counter (one 32-bit word)
+  long long cls_off;   // image classification word
+  const float* image;  // for the classification
+  long long nimg;      // C * N
+};
+
+// Tile geometry of the batched kernels (3D plane tile TP3 x TQ3, 2D row tile TQ2).
+constexpr int kTP3 = 16, kTQ3 = 16, kTQ2 = 256;
+
+// Chunk lengths of the two batched kernel classes: class 0 for single-channel
+// batches, class 1 for up to 4 channels.
+constexpr int kBatchK3[2] = {8, 4};
+constexpr int kBatchK2[2] = {32, 16};
+constexpr int kBatchMaxC[2] = {1, 4};
+
+size_t batched_lds_bytes(int kclass, int C, bool has2d, bool has3d);
+int batched_capacity(int kclass, bool rec, size_t lds);
+hipError_t launch_batched(int kclass, bool rec, const BatchInst* insts, int ninst, const PassDesc* passes,
+                          unsigned char* ws, int grid, size_t lds, unsigned long long spin_limit, hipStream_t stream);
+hipError_t launch_batched_classify(const BatchInst* insts, int ninst, unsigned char* ws, hipStream_t stream);
+
+// Chunk length of the backward kernels for a geometry (0 if none fits).
+int bwd_chunk_for(int ndim, int C, bool scan_contiguous);
+hipError_t launch_bwd_pass(const BwdDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
+                           hipStream_t stream);
+size_t batched_bwd_lds_bytes(int C, bool has2d, bool has3d);
+int batched_bwd_capacity(size_t lds);
+hipError_t launch_batched_bwd(const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws, int grid,
+                              size_t lds, unsigned long long spin_limit, hipStream_t stream);
+// Chunk lengths of the batched backward kernel.
+constexpr int kBwdBatchK3 = 4, kBwdBatchK2 = 16;
 
 // Pick the chunk length for a tile geometry so that the kernel's LDS fits.
 // Returns 0 if no instantiation fits (too many channels).

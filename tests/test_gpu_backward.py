@@ -1,0 +1,129 @@
+"""GPU backward (reverse of the recorded schedule) vs the CPU oracle.
+
+The kernels accumulate every adjoint in the same order as the oracle's FP32
+reverse pass, so dL/dI and dL/dM are expected bitwise equal (the bar is 1e-5
+relative).  The oracle's FP64 gradient is pinned to central finite differences
+in test_oracle.py; here the GPU gradient is also checked against FP64 central
+differences directly, away from argmin ties."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DEV, assert_parity, to_dev, to_host
+from paper_2208_00001_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((23, 31, 19), 1, 0.7, 2), ((17, 40, 36), 1, 1.0, 2), ((30, 21, 18), 1, 0.0, 1), ((19, 26, 33), 2, 0.4, 1),
+         ((300, 270), 1, 0.7, 2), ((270, 300), 2, 0.5, 2), ((1, 40, 37), 1, 0.6, 1), ((33, 1, 20), 1, 1.0, 2),
+         ((5, 6, 7), 1, 0.8, 3), ((64, 17, 35), 3, 0.3, 1)]
+
+
+def gpu_fwd_bwd(c, W):
+    from paper_2208_00001_amd import binding as B
+    img, m = to_dev(c["image"]), to_dev(c["mask"])
+    out, rec = B.ggdt_forward_rec(img, m, c["spacing"], c["v"], c["lam"], c["iterations"])
+    gi, gm = B.ggdt_backward(img, rec, to_dev(W), c["spacing"], c["v"], c["lam"], c["iterations"])
+    return to_host(out), to_host(rec), to_host(gi), to_host(gm)
+
+
+@pytest.mark.parametrize("shape,C,lam,it", CASES, ids=lambda v: str(v))
+def test_backward_matches_oracle_f32(shape, C, lam, it):
+    c = synth.small_case(shape, C=C, seed=700 + len(shape) * 7 + C, lam=lam, iterations=it, soft=True, v=10.0)
+    W = np.random.default_rng(701).standard_normal(shape).astype(np.float32)
+    print(f"case {c['name']} lam={c['lam']} it={it}", flush=True)
+    out, rec, gi, gm = gpu_fwd_bwd(c, W)
+    ref, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], it, "f32", records=True)
+    assert np.array_equal(out, ref) and np.array_equal(rec, ref_rec)
+    rgi, rgm = oracle.backward(c["image"], ref_rec, W, c["spacing"], c["v"], c["lam"], it, "f32")
+    assert assert_parity(gm, rgm, what="dL/dM"), "dL/dM not bitwise"
+    assert assert_parity(gi.reshape(rgi.shape), rgi, what="dL/dI"), "dL/dI not bitwise"
+
+
+def test_autograd_function():
+    from paper_2208_00001_amd.binding import GGDTFunction
+    c = synth.small_case((20, 24, 22), C=1, seed=702, lam=0.7, iterations=2, soft=True, v=10.0)
+    W = np.random.default_rng(703).standard_normal(c["mask"].shape).astype(np.float32)
+    img = to_dev(c["image"][0]).requires_grad_(True)
+    m = to_dev(c["mask"]).requires_grad_(True)
+    D = GGDTFunction.apply(img, m, c["spacing"], c["v"], c["lam"], c["iterations"])
+    (D * to_dev(W)).sum().backward()
+    _, rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 2, "f32", records=True)
+    rgi, rgm = oracle.backward(c["image"], rec, W, c["spacing"], c["v"], c["lam"], 2, "f32")
+    assert np.array_equal(to_host(m.grad), rgm)
+    assert np.array_equal(to_host(img.grad), rgi[0])
+
+
+def test_gpu_gradient_vs_central_differences():
+    """FP64 central differences (eps = 1e-3 on M and on I) on voxels whose FP64
+    records do not change under +-eps; GPU FP32 gradient within 1e-3 relative."""
+    c = synth.small_case((14, 15, 13), C=1, seed=704, lam=0.7, iterations=3, soft=True, v=10.0)
+    W = np.random.default_rng(705).standard_normal(c["mask"].shape)
+    _, _, gi, gm = gpu_fwd_bwd(c, W.astype(np.float32))
+    img = c["image"].astype(np.float64)
+    msk = c["mask"].astype(np.float64)
+
+    def loss(i2, m2):
+        D, rec = oracle.ggdt(i2, m2, c["spacing"], c["v"], c["lam"], 3, "f64", records=True)
+        return float(np.sum(W * D)), rec
+
+    _, rec0 = loss(img, msk)
+    rgi64, rgm64 = oracle.backward(img, rec0, W, c["spacing"], c["v"], c["lam"], 3, "f64")
+    rng = np.random.default_rng(706)
+    eps = 1e-3
+    checked = 0
+    for _ in range(120):
+        idx = tuple(int(rng.integers(0, s)) for s in msk.shape)
+        for which in ("M", "I"):
+            vals, same = [], True
+            for sgn in (1, -1):
+                i2, m2 = img.copy(), msk.copy()
+                if which == "M":
+                    m2[idx] += sgn * eps
+                else:
+                    i2[(0,) + idx] += sgn * eps
+                L, rec = loss(i2, m2)
+                same &= np.array_equal(rec, rec0)
+                vals.append(L)
+            if not same:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            an64 = rgm64[idx] if which == "M" else rgi64[(0,) + idx]
+            an = gm[idx] if which == "M" else gi.reshape(img.shape)[(0,) + idx]
+            if abs(an - an64) > 1e-4 * max(abs(an64), 1.0):
+                continue  # FP32 and FP64 schedules took different argmins on this voxel's paths
+            assert abs(an - fd) <= 1e-3 * abs(fd) + 1e-3, (which, idx, an, fd)
+            checked += 1
+    assert checked >= 100
+
+
+def test_config5_batched_forward_backward():
+    """4 x 128^3, lambda 0.7, soft mask, v = 10: one batched forward (with records)
+    and one batched backward; every volume equals its single-instance launches,
+    and volume 0 equals the oracle's FP32 forward and reverse pass."""
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd.batched import BatchedPlan
+    cases = synth.config5()
+    inst = [dict(image=to_dev(c["image"]), softmask=to_dev(c["mask"]), spacing=c["spacing"], v=c["v"], lam=c["lam"],
+                 iterations=c["iterations"], records=True, grad_out=to_dev(c["weight"])) for c in cases]
+    plan = BatchedPlan(inst)
+    print("plan", plan.info(), flush=True)
+    plan.run()
+    assert plan.status() == 0, "watchdog fired in the batched forward"
+    grads = plan.backward()
+    torch.cuda.synchronize()
+    assert plan.status() == 0, "watchdog fired in the batched backward"
+    for k, (c, d) in enumerate(zip(cases, plan.inst)):
+        out, rec = B.ggdt_forward_rec(d["image"], d["softmask"], c["spacing"], c["v"], c["lam"], c["iterations"])
+        gi, gm = B.ggdt_backward(d["image"], rec, d["grad_out"], c["spacing"], c["v"], c["lam"], c["iterations"])
+        assert torch.equal(out, d["out"]) and torch.equal(rec, d["records"]), f"volume {k} forward"
+        assert torch.equal(gi, grads[k][0]) and torch.equal(gm, grads[k][1]), f"volume {k} backward"
+    c = cases[0]
+    ref, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], c["iterations"], "f32",
+                               records=True)
+    assert np.array_equal(to_host(plan.inst[0]["out"]), ref)
+    rgi, rgm = oracle.backward(c["image"], ref_rec, c["weight"], c["spacing"], c["v"], c["lam"], c["iterations"], "f32")
+    assert assert_parity(to_host(grads[0][1]), rgm, what="dL/dM"), "dL/dM not bitwise"
+    assert assert_parity(to_host(grads[0][0]), rgi, what="dL/dI"), "dL/dI not bitwise"
+    plan.close()
