@@ -40,6 +40,18 @@ struct BLayout {
   }
 };
 
+__device__ __forceinline__ float pick(bool c, float x, float y) { return c ? x : y; }
+
+// A[j] for a j known only at run time (taken from a record), by an unrolled
+// select of values: indexing the array directly (or selecting between array
+// elements as lvalues) would move the descriptor copy to private scratch memory.
+__device__ __forceinline__ float spatial_term(const BwdDesc& g, int j) {
+  float a = g.A[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) a = pick(j == k, g.A[k], a);
+  return a;
+}
+
 // Edge cost w(x, y) through offset j, from the staged image (x and y addresses
 // of channel 0; channels are `cstride` apart).
 template <int MODE>
@@ -51,7 +63,7 @@ __device__ __forceinline__ float bwd_edge(const BwdDesc& g, int j, const float* 
     const float dc = sx[c * cstride] - sy[c * cstride];
     s = fmaf(dc, dc, s);
   }
-  return sqrtf(fmaf(g.lam, s, g.A[j]));
+  return sqrtf(fmaf(g.lam, s, spatial_term(g, j)));
 }
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE>
@@ -106,7 +118,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
               const float dc = g.image[(long long)c * g.N + x] - g.image[(long long)c * g.N + y];
               s = fmaf(dc, dc, s);
             }
-            w = sqrtf(fmaf(g.lam, s, g.A[j]));
+            w = sqrtf(fmaf(g.lam, s, spatial_term(g, j)));
           }
           if (w > 0.0f) {
             const float coef = (a * g.lam) / w;
@@ -141,6 +153,11 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
       const int p0 = tp * TP, q0 = tq * TQ;
       const int bp0 = (NDIM == 3) ? p0 - K : 0;
       const int bq0 = q0 - K;
+      // the thread index, opaque to the optimiser: per-thread index math of the
+      // unrolled staging loops below is then recomputed per tile instead of being
+      // hoisted out of the chunk loop and held in registers for the whole pass
+      int tid = threadIdx.x;
+      __asm__ volatile("" : "+v"(tid));
 
       // 1. abar_in (m = 1..kk, and m = 0 in chunk 0) and the image (m = 0..mtop)
       // into LDS; expansion of plane m is kk - m (image: at least 1).
@@ -171,14 +188,16 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
             __builtin_amdgcn_global_load_lds(g.image + (long long)ch * g.N + x, StI + ch * STAGE + f0 + wave0, 4, 0,
                                              0);
       }
-      // records (m = 0..kk) through registers: all byte loads first, then the LDS
-      // stores; out-of-plane and unneeded cells read as 0 ("kept").
-      {
-        constexpr int NR = (STAGE + kThreads - 1) / kThreads;
-        unsigned rv[NR];
+      // records (m = 0..kk) through registers, in batches of RB byte loads
+      // issued together before their LDS stores (the batch bounds the registers
+      // held); out-of-plane and unneeded cells read as 0 ("kept").
+      constexpr int NR = (STAGE + kThreads - 1) / kThreads;
+      constexpr int RB = NR < 8 ? NR : 8;
+      for (int n0 = 0; n0 < NR; n0 += RB) {
+        unsigned rv[RB];
 #pragma unroll
-        for (int n = 0; n < NR; ++n) {
-          const int f = n * kThreads + tid;
+        for (int n1 = 0; n1 < RB; ++n1) {
+          const int f = (n0 + n1) * kThreads + tid;
           int m, lx, k;
           if (SCANC) {
             lx = f / SC;
@@ -195,12 +214,12 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
           const int pp = bp0 + br, qq = bq0 + bc;
           const bool in = f < STAGE && m >= 0 && m <= kk && k >= 0 && k < Na && qq >= 0 && qq < Nq &&
                           (NDIM == 2 || (pp >= 0 && pp < Np)) && outside<NDIM, TP, TQ>(pp, qq, p0, q0) <= kk - m;
-          rv[n] = in ? (unsigned)g.rec[k * g.sa + pp * g.sp + qq * g.sq] : 0u;
+          rv[n1] = in ? (unsigned)g.rec[k * g.sa + pp * g.sp + qq * g.sq] : 0u;
         }
 #pragma unroll
-        for (int n = 0; n < NR; ++n) {
-          const int f = n * kThreads + tid;
-          if (f < STAGE) StR[f] = (unsigned char)rv[n];
+        for (int n1 = 0; n1 < RB; ++n1) {
+          const int f = (n0 + n1) * kThreads + tid;
+          if (f < STAGE) StR[f] = (unsigned char)rv[n1];
         }
       }
       // own Ibar of the parent planes m = 1..kk
