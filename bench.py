@@ -73,6 +73,27 @@ def cpu_baseline(c):
             "sample": f"1 iteration (6 passes) of the {c['name']} volume, {vu} voxel-updates in {dt:.1f} s"}
 
 
+def calibrate_copy(mib):
+    """One launch of the scale kernel over a (mib MiB) volume: reads the mask and
+    writes the output once each, a plain streaming copy of known size."""
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+
+    dev = "cuda:0"
+    plane = 512 * 512
+    n = max(1, mib * 2**20 // 4 // plane) * plane
+    shape = (n // plane, 512, 512)
+    src = torch.rand(shape, device=dev)
+    dst = torch.empty(shape, device=dev)
+    ws = B.new_workspace(shape, 1, dev)
+    torch.cuda.synchronize()
+    B.ggdt3d(src, src, (1.0, 1.0, 1.0), 2.0, 1.0, 0, out=dst, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src * 2.0)
+    return {"kernel": "scale_kernel", "bytes_read": 4 * n, "bytes_written": 4 * n}
+
+
 def _time(fn, reps):
     import torch
     ts = []
@@ -171,6 +192,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and backward comparisons")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the measurements, run the elementwise scale kernel (D = v*M, zero iterations) once "
+                         "over a MIB-sized volume: one read and one write of known size, the reference for scaling "
+                         "HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this path has no multi-GPU mode (asked for --gpus {args.gpus})",
@@ -249,6 +274,8 @@ def main():
     if not args.no_batched:
         line["batched"] = bench_batched(max(3, min(args.steps, 10)))
         line["backward"] = bench_backward(max(3, min(args.steps, 10)))
+    if args.calibrate_copy > 0:
+        line["calibration"] = calibrate_copy(args.calibrate_copy)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(line), flush=True)
