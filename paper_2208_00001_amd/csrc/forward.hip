@@ -1,6 +1,7 @@
 // Forward directional-pass kernels for gfx950: one launch per pass of one
 // instance (see pass_device.h for the pass itself), plus the small helper
 // kernels (workspace reset, image classification, v * M).
+#include "pass_cell.h"
 #include "pass_device.h"
 
 namespace ggdt {
@@ -16,7 +17,32 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* wo
                                                     xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// Single-channel 3D passes on 16 x 16 tiles with K = 8: one thread per box cell.
+template <int RMODE, bool REC>
+__global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, unsigned* words,
+                                                                 unsigned long long limit) {
+  __shared__ float2 pair[2 * kCellThreads];
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  run_pass_cell_mode<RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, pair,
+                                 xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
 using PassKernel = void (*)(PassDesc, unsigned*, unsigned long long);
+
+bool use_cell_path(const PassDesc& d, int ndim) {
+  return ndim == 3 && d.C == 1 && d.TP == kCellTP && d.TQ == kCellTQ && d.K == kCellK;
+}
+
+PassKernel select_cell_kernel(const PassDesc& d) {
+  if (d.rec) {
+    if (d.mode == kModeLam0) return pass_cell_kernel<kModeLam0, true>;
+    if (d.mode == kModeLam1C1) return pass_cell_kernel<kModeLam1C1, true>;
+    return pass_cell_kernel<kModeGeneral, true>;
+  }
+  if (d.mode == kModeLam0) return pass_cell_kernel<kModeLam0, false>;
+  if (d.mode == kModeLam1C1) return pass_cell_kernel<kModeLam1C1, false>;
+  return pass_cell_kernel<kModeGeneral, false>;
+}
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC>
 PassKernel pick_mode(int mode, bool rec) {
@@ -95,6 +121,7 @@ __global__ void scale_kernel(const float* mask, float v, float* out, long long n
 struct CapEntry {
   const void* fn;
   size_t lds;
+  int threads;
   int cap;
 };
 CapEntry g_cap_cache[256];
@@ -102,17 +129,18 @@ int g_cap_n = 0;
 
 // Co-resident workgroups of `fn` with `lds` dynamic LDS bytes (also raises the
 // kernel's dynamic-LDS limit once).  0 on failure.
-int capacity_for(PassKernel fn, size_t lds) {
+int capacity_for(PassKernel fn, size_t lds, int threads = kThreads) {
   for (int i = 0; i < g_cap_n; ++i)
-    if (g_cap_cache[i].fn == (const void*)fn && g_cap_cache[i].lds == lds) return g_cap_cache[i].cap;
+    if (g_cap_cache[i].fn == (const void*)fn && g_cap_cache[i].lds == lds && g_cap_cache[i].threads == threads)
+      return g_cap_cache[i].cap;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kThreads, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, threads, lds) != hipSuccess) return 0;
   const int cap = per_cu * cus;
-  if (g_cap_n < 256) g_cap_cache[g_cap_n++] = CapEntry{(const void*)fn, lds, cap};
+  if (g_cap_n < 256) g_cap_cache[g_cap_n++] = CapEntry{(const void*)fn, lds, threads, cap};
   return cap;
 }
 
@@ -129,6 +157,15 @@ int pass_chunk_for(int ndim, int C, bool scan_contiguous) {
 
 hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
                        hipStream_t stream) {
+  if (use_cell_path(d, ndim)) {
+    PassKernel fn = select_cell_kernel(d);
+    const int cap = capacity_for(fn, 0, kCellThreads);
+    if (cap <= 0) return hipErrorInvalidConfiguration;
+    const int ntiles = d.ntp * d.ntq;
+    const int grid = ntiles < cap ? ntiles : cap;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), 0, stream, d, words, spin_limit);
+    return hipGetLastError();
+  }
   PassKernel fn = select_kernel(d, ndim);
   if (!fn) return hipErrorInvalidConfiguration;
   const size_t lds = lds_bytes_for(ndim, d.K, d.C, d.sa == 1);
