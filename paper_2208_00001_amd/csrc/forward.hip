@@ -18,13 +18,13 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* wo
 }
 
 // Single-channel 3D passes on 16 x 16 tiles with K = 8: one thread per box cell.
-template <int RMODE, bool REC>
+template <bool SCANC, int RMODE, bool REC>
 __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, unsigned* words,
                                                                  unsigned long long limit) {
-  __shared__ float2 pair[2 * kCellThreads];
+  extern __shared__ float lds[];
   if (ld_relaxed(words + kWordAbort) != 0u) return;
-  run_pass_cell_mode<RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, pair,
-                                 xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+  run_pass_cell_mode<SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
+                                        xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 using PassKernel = void (*)(PassDesc, unsigned*, unsigned long long);
@@ -33,15 +33,20 @@ bool use_cell_path(const PassDesc& d, int ndim) {
   return ndim == 3 && d.C == 1 && d.TP == kCellTP && d.TQ == kCellTQ && d.K == kCellK;
 }
 
-PassKernel select_cell_kernel(const PassDesc& d) {
+template <bool SCANC>
+PassKernel select_cell_mode(const PassDesc& d) {
   if (d.rec) {
-    if (d.mode == kModeLam0) return pass_cell_kernel<kModeLam0, true>;
-    if (d.mode == kModeLam1C1) return pass_cell_kernel<kModeLam1C1, true>;
-    return pass_cell_kernel<kModeGeneral, true>;
+    if (d.mode == kModeLam0) return pass_cell_kernel<SCANC, kModeLam0, true>;
+    if (d.mode == kModeLam1C1) return pass_cell_kernel<SCANC, kModeLam1C1, true>;
+    return pass_cell_kernel<SCANC, kModeGeneral, true>;
   }
-  if (d.mode == kModeLam0) return pass_cell_kernel<kModeLam0, false>;
-  if (d.mode == kModeLam1C1) return pass_cell_kernel<kModeLam1C1, false>;
-  return pass_cell_kernel<kModeGeneral, false>;
+  if (d.mode == kModeLam0) return pass_cell_kernel<SCANC, kModeLam0, false>;
+  if (d.mode == kModeLam1C1) return pass_cell_kernel<SCANC, kModeLam1C1, false>;
+  return pass_cell_kernel<SCANC, kModeGeneral, false>;
+}
+
+PassKernel select_cell_kernel(const PassDesc& d) {
+  return d.sa == 1 ? select_cell_mode<true>(d) : select_cell_mode<false>(d);
 }
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC>
@@ -159,11 +164,12 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
                        hipStream_t stream) {
   if (use_cell_path(d, ndim)) {
     PassKernel fn = select_cell_kernel(d);
-    const int cap = capacity_for(fn, 0, kCellThreads);
+    const size_t lds = cell_lds_bytes(d.sa == 1);
+    const int cap = capacity_for(fn, lds, kCellThreads);
     if (cap <= 0) return hipErrorInvalidConfiguration;
     const int ntiles = d.ntp * d.ntq;
     const int grid = ntiles < cap ? ntiles : cap;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), 0, stream, d, words, spin_limit);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), lds, stream, d, words, spin_limit);
     return hipGetLastError();
   }
   PassKernel fn = select_kernel(d, ndim);

@@ -22,6 +22,18 @@ namespace dev {
 constexpr int kCellTP = 16, kCellTQ = 16, kCellK = 8;
 constexpr int kCellBQ = kCellTQ + 2 * kCellK;          // 32: box row length
 constexpr int kCellThreads = kCellBQ * kCellBQ;         // 1024: one thread per box cell
+// Scan-contiguous layout: per box cell a run of kCellSC consecutive memory
+// positions along the scan axis (K + 1 planes and up to 3 alignment slots,
+// starting at a multiple of 4), and the own cells' results at an odd stride.
+constexpr int kCellSC = 4 * ((kCellK + 4 + 3) / 4);    // 12
+constexpr int kCellSCR = kCellK + 1;                     // 9
+constexpr int kCellStage = kCellThreads * kCellSC;       // floats of one staged array
+// LDS bytes: two (D, I) pair planes; with the scan axis contiguous also the staged
+// D_old and image runs and the results.
+constexpr size_t cell_lds_bytes(bool scanc) {
+  return sizeof(float) * ((size_t)4 * kCellThreads +
+                          (scanc ? (size_t)2 * kCellStage + (size_t)kCellTP * kCellTQ * kCellSCR : 0));
+}
 
 template <int MODE>
 __device__ __forceinline__ float cell_edge(const PassDesc& g, int j, float ix, float iy) {
@@ -32,11 +44,15 @@ __device__ __forceinline__ float cell_edge(const PassDesc& g, int j, float ix, f
 }
 
 // One pass of one single-channel 3D instance by workgroup `wg` of G (blockDim
-// = 1024).  `pair` holds 2 x 1024 float2 of LDS.  False if a bounded wait gave up.
-template <int MODE, bool REC>
+// = 1024), `lds` laid out as cell_lds_bytes(SCANC) describes.  SCANC: the scan
+// axis is the contiguous memory axis; a thread's planes are then consecutive
+// floats, and are gathered through LDS by 16-byte runs instead of one load per
+// lane and plane.  False if a bounded wait gave up.
+template <bool SCANC, int MODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
-                                              unsigned long long limit, float2* pair, int wg, int G) {
+                                              unsigned long long limit, float* lds, int wg, int G) {
   constexpr int TP = kCellTP, TQ = kCellTQ, K = kCellK, BQ = kCellBQ, NB = kCellThreads;
+  constexpr int SC = kCellSC, SCR = kCellSCR, STAGE = kCellStage;
   const PassDesc g = *gp;
   const int tid = threadIdx.x;
   const int br = tid / BQ, bc = tid - br * BQ;
@@ -46,8 +62,14 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   const int ntiles = g.ntp * g.ntq;
   const int Na = g.Na, Np = g.Np, Nq = g.Nq;
   constexpr bool USE_I = MODE != kModeLam0;
-  float2* const P0 = pair;
-  float2* const P1 = pair + NB;
+  float2* const P0 = reinterpret_cast<float2*>(lds);
+  float2* const P1 = P0 + NB;
+  float* const StD = lds + 4 * NB;  // SCANC only
+  float* const StI = StD + STAGE;
+  float* const Res = StI + STAGE;
+  const int wave0 = tid & ~63;
+  // 16-byte runs need every run start 16-byte aligned
+  const bool vec4s = SCANC && (Na & 3) == 0 && (g.sp & 3) == 0 && (g.sq & 3) == 0;
 
   // First plane in scan order (never changed by the pass): written when the
   // pass initialises D, recorded as "keep" when records are asked for.
@@ -85,15 +107,78 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
       // 1. This cell's image and D_old on the planes where it is needed: plane
       // j is used by the cells within distance kk - j of the tile.
       float ix[K + 1], dd[K + 1];
+      if (SCANC) {
+        // Memory positions kb .. kb + SC - 1 of every box cell, cell-major;
+        // plane j sits in slot sbase + sign * j.
+        const int kmin = g.sign > 0 ? t0 - 1 : Na - t0 - kk;
+        const int kb = kmin & ~3;
+        const int sbase = g.sign > 0 ? t0 - 1 - kb : Na - t0 - kb;
+        // the thread index, opaque to the optimiser: the staging index math is
+        // recomputed per tile instead of being hoisted out of the chunk loop
+        // and held in registers for the whole pass
+        int stid = tid;
+        __asm__ volatile("" : "+v"(stid));
+        if (vec4s) {
+          constexpr int GPC = SC / 4;  // 16-byte groups per cell
+          constexpr int NG = STAGE / 4;
 #pragma unroll
-      for (int j = 0; j <= K; ++j) {
-        const bool need = in && j <= kk && e <= kk - j;
-        ix[j] = 0.0f;
-        dd[j] = 0.0f;
-        if (need) {
-          const int x = xof(j);
-          if (USE_I) ix[j] = g.image[x];
-          if (j >= 1 || c == 0) dd[j] = dsrc0[x];
+          for (int g0 = 0; g0 < NG; g0 += NB) {
+            const int gi = g0 + stid;
+            const int lx = gi / GPC, gg = gi - lx * GPC;
+            const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+            const int cpp = p0 - K + cbr, cqq = q0 - K + cbc;
+            const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+            const int k0 = kb + 4 * gg;
+            const bool ok = k0 + 3 <= Na - 1 && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+            // planes j held by this group, and the highest plane this cell needs
+            const int jlo = g.sign > 0 ? k0 - (t0 - 1) : (Na - t0) - (k0 + 3);
+            const int jtop = min(jlo + 3, kk - ce);
+            if (ok) {
+              const int x = k0 + cpp * g.sp + cqq * g.sq;
+              if (max(jlo, c == 0 ? 0 : 1) <= jtop)
+                __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + 4 * (g0 + wave0), 16, 0, 0);
+              if (USE_I && max(jlo, 0) <= jtop)
+                __builtin_amdgcn_global_load_lds(g.image + x, StI + 4 * (g0 + wave0), 16, 0, 0);
+            }
+          }
+        } else {
+#pragma unroll 1
+          for (int f0 = 0; f0 < STAGE; f0 += NB) {
+            const int f = f0 + stid;
+            const int lx = f / SC, sl = f - lx * SC;
+            const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+            const int cpp = p0 - K + cbr, cqq = q0 - K + cbc;
+            const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+            const int k = kb + sl;
+            const int j = g.sign > 0 ? k - (t0 - 1) : (Na - t0) - k;
+            const bool ok = j >= 0 && j <= kk && ce <= kk - j && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+            if (ok) {
+              const int x = k + cpp * g.sp + cqq * g.sq;
+              if (j >= 1 || c == 0) __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + f0 + wave0, 4, 0, 0);
+              if (USE_I) __builtin_amdgcn_global_load_lds(g.image + x, StI + f0 + wave0, 4, 0, 0);
+            }
+          }
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // the global->LDS copies have landed
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j <= K; ++j) {
+          const bool need = in && j <= kk && e <= kk - j;
+          const int sl = tid * SC + sbase + g.sign * j;
+          ix[j] = (USE_I && need) ? StI[sl] : 0.0f;
+          dd[j] = (need && (j >= 1 || c == 0)) ? StD[sl] : 0.0f;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j <= K; ++j) {
+          const bool need = in && j <= kk && e <= kk - j;
+          ix[j] = 0.0f;
+          dd[j] = 0.0f;
+          if (need) {
+            const int x = xof(j);
+            if (USE_I) ix[j] = g.image[x];
+            if (j >= 1 || c == 0) dd[j] = dsrc0[x];
+          }
         }
       }
 
@@ -164,7 +249,10 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
           Pc[tid] = make_float2(best, ixj);
           if (e == 0) {
             const int x = xof(i + 1);
-            g.D[x] = best;
+            if (SCANC)
+              Res[own_slot * SCR + i] = best;
+            else
+              g.D[x] = best;
             if (REC && g.rec) g.rec[x] = (uint8_t)choice;
             if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
           }
@@ -174,6 +262,22 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         Pp = Pc;
         Pc = t;
       }
+
+      // 4. Scan-contiguous results: each own cell's kk planes as one run of
+      // consecutive memory positions, eight lanes per cell.
+      if (SCANC) {
+#pragma unroll
+        for (int f0 = 0; f0 < TP * TQ * K; f0 += NB) {
+          const int f = f0 + tid;
+          const int own = f / K, i = f - own * K;
+          const int opp = p0 + own / TQ, oqq = q0 + (own - (own / TQ) * TQ);
+          if (i < kk && opp < Np && oqq < Nq) {
+            const int t = t0 + i;
+            g.D[(g.sign > 0 ? t : Na - 1 - t) + opp * g.sp + oqq * g.sq] = Res[own * SCR + i];
+          }
+        }
+        // Res is rewritten only after the next staging barrier.
+      }
     }
   }
   return true;
@@ -181,15 +285,15 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
 
 // Requested mode RMODE falls back to the general formula when the image
 // classification word rules the fast edge cost out.
-template <int RMODE, bool REC>
+template <bool SCANC, int RMODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
-                                                   const unsigned* cls_word, unsigned long long limit, float2* pair,
+                                                   const unsigned* cls_word, unsigned long long limit, float* lds,
                                                    int wg, int G) {
-  if (RMODE == kModeGeneral) return run_pass_cell<kModeGeneral, REC>(gp, xbuf, words, limit, pair, wg, G);
+  if (RMODE == kModeGeneral) return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
-  if (fast) return run_pass_cell<RMODE, REC>(gp, xbuf, words, limit, pair, wg, G);
-  return run_pass_cell<kModeGeneral, REC>(gp, xbuf, words, limit, pair, wg, G);
+  if (fast) return run_pass_cell<SCANC, RMODE, REC>(gp, xbuf, words, limit, lds, wg, G);
+  return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
 }
 
 }  // namespace dev
