@@ -87,198 +87,242 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   }
 
   const float* const dsrc0 = g.init ? g.mask : g.D;
-  for (int c = 0; c < g.nchunk; ++c) {
-    const int t0 = 1 + c * K;  // scan position of the chunk's first computed plane
-    const int kk = min(K, Na - t0);
-    const unsigned epoch_in = g.epoch_base + (unsigned)c;
-    const unsigned epoch_out = epoch_in + 1u;
-    for (int tile = wg; tile < ntiles; tile += G) {
-      const int tp = tile / g.ntq, tq = tile - tp * g.ntq;
-      const int p0 = tp * TP, q0 = tq * TQ;
-      const int pp = p0 - K + br, qq = q0 - K + bc;
-      const bool in = pp >= 0 && pp < Np && qq >= 0 && qq < Nq;
-      const int xpq = in ? pp * g.sp + qq * g.sq : 0;
-      // memory index of plane j of the chunk (scan position t0 - 1 + j)
-      auto xof = [&](int j) {
-        const int t = t0 - 1 + j;
-        return (g.sign > 0 ? t : Na - 1 - t) * g.sa + xpq;
-      };
+  // Work items in order: chunk-major, then this workgroup's tiles.  The next
+  // item's image and D_old are fetched while the current item's planes are
+  // advanced (into registers, or into the LDS staging area once the current
+  // item has copied its values out of it).
+  const int nmine = (ntiles - wg + G - 1) / G;  // grid <= ntiles, so >= 1
+  const int nitems = g.nchunk * nmine;
+  struct Item {
+    int c, t0, kk, tile, p0, q0, pp, qq, xpq;
+    bool in;
+  };
+  auto item_of = [&](int n) {
+    Item it;
+    it.c = n / nmine;
+    it.tile = wg + (n - it.c * nmine) * G;
+    it.t0 = 1 + it.c * K;  // scan position of the chunk's first computed plane
+    it.kk = min(K, Na - it.t0);
+    const int tp = it.tile / g.ntq, tq = it.tile - tp * g.ntq;
+    it.p0 = tp * TP;
+    it.q0 = tq * TQ;
+    it.pp = it.p0 - K + br;
+    it.qq = it.q0 - K + bc;
+    it.in = it.pp >= 0 && it.pp < Np && it.qq >= 0 && it.qq < Nq;
+    it.xpq = it.in ? it.pp * g.sp + it.qq * g.sq : 0;
+    return it;
+  };
+  // memory index of plane j of an item's chunk (scan position t0 - 1 + j)
+  auto xof = [&](const Item& it, int j) {
+    const int t = it.t0 - 1 + j;
+    return (g.sign > 0 ? t : Na - 1 - t) * g.sa + it.xpq;
+  };
+  // Slot of plane j in a cell's staged run (scan-contiguous layout): the run
+  // holds memory positions kb .. kb + SC - 1, kb the chunk's lowest position
+  // rounded down to a multiple of 4.
+  auto run_start = [&](const Item& it) {
+    const int kmin = g.sign > 0 ? it.t0 - 1 : Na - it.t0 - it.kk;
+    return kmin & ~3;
+  };
+  auto slot_base = [&](const Item& it, int kb) { return g.sign > 0 ? it.t0 - 1 - kb : Na - it.t0 - kb; };
 
-      // 1. This cell's image and D_old on the planes where it is needed: plane
-      // j is used by the cells within distance kk - j of the tile.
-      float ix[K + 1], dd[K + 1];
-      if (SCANC) {
-        // Memory positions kb .. kb + SC - 1 of every box cell, cell-major;
-        // plane j sits in slot sbase + sign * j.
-        const int kmin = g.sign > 0 ? t0 - 1 : Na - t0 - kk;
-        const int kb = kmin & ~3;
-        const int sbase = g.sign > 0 ? t0 - 1 - kb : Na - t0 - kb;
-        // the thread index, opaque to the optimiser: the staging index math is
-        // recomputed per tile instead of being hoisted out of the chunk loop
-        // and held in registers for the whole pass
-        int stid = tid;
-        __asm__ volatile("" : "+v"(stid));
-        if (vec4s) {
-          constexpr int GPC = SC / 4;  // 16-byte groups per cell
-          constexpr int NG = STAGE / 4;
+  // Plane j of an item is used by the cells within distance kk - j of the tile.
+  float nx[K + 1], nd[K + 1];
+  auto fetch_regs = [&](const Item& it) {
 #pragma unroll
-          for (int g0 = 0; g0 < NG; g0 += NB) {
-            const int gi = g0 + stid;
-            const int lx = gi / GPC, gg = gi - lx * GPC;
-            const int cbr = lx / BQ, cbc = lx - cbr * BQ;
-            const int cpp = p0 - K + cbr, cqq = q0 - K + cbc;
-            const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
-            const int k0 = kb + 4 * gg;
-            const bool ok = k0 + 3 <= Na - 1 && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
-            // planes j held by this group, and the highest plane this cell needs
-            const int jlo = g.sign > 0 ? k0 - (t0 - 1) : (Na - t0) - (k0 + 3);
-            const int jtop = min(jlo + 3, kk - ce);
-            if (ok) {
-              const int x = k0 + cpp * g.sp + cqq * g.sq;
-              if (max(jlo, c == 0 ? 0 : 1) <= jtop)
-                __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + 4 * (g0 + wave0), 16, 0, 0);
-              if (USE_I && max(jlo, 0) <= jtop)
-                __builtin_amdgcn_global_load_lds(g.image + x, StI + 4 * (g0 + wave0), 16, 0, 0);
-            }
-          }
-        } else {
-#pragma unroll 1
-          for (int f0 = 0; f0 < STAGE; f0 += NB) {
-            const int f = f0 + stid;
-            const int lx = f / SC, sl = f - lx * SC;
-            const int cbr = lx / BQ, cbc = lx - cbr * BQ;
-            const int cpp = p0 - K + cbr, cqq = q0 - K + cbc;
-            const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
-            const int k = kb + sl;
-            const int j = g.sign > 0 ? k - (t0 - 1) : (Na - t0) - k;
-            const bool ok = j >= 0 && j <= kk && ce <= kk - j && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
-            if (ok) {
-              const int x = k + cpp * g.sp + cqq * g.sq;
-              if (j >= 1 || c == 0) __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + f0 + wave0, 4, 0, 0);
-              if (USE_I) __builtin_amdgcn_global_load_lds(g.image + x, StI + f0 + wave0, 4, 0, 0);
-            }
-          }
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // the global->LDS copies have landed
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j <= K; ++j) {
-          const bool need = in && j <= kk && e <= kk - j;
-          const int sl = tid * SC + sbase + g.sign * j;
-          ix[j] = (USE_I && need) ? StI[sl] : 0.0f;
-          dd[j] = (need && (j >= 1 || c == 0)) ? StD[sl] : 0.0f;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j <= K; ++j) {
-          const bool need = in && j <= kk && e <= kk - j;
-          ix[j] = 0.0f;
-          dd[j] = 0.0f;
-          if (need) {
-            const int x = xof(j);
-            if (USE_I) ix[j] = g.image[x];
-            if (j >= 1 || c == 0) dd[j] = dsrc0[x];
-          }
-        }
-      }
-
-      // 2. Plane 0 of the chunk: the pass's first plane in chunk 0, else the
-      // values the previous chunk published (this tile's and its neighbours').
-      float d0 = __builtin_inff();
-      int fail = 0;
-      if (in && e <= kk) {
-        if (c == 0) {
-          d0 = g.init ? g.v * dd[0] : dd[0];
-        } else {
-          const int otp = pp / TP, otq = qq / TQ;
-          const int slot = (pp - otp * TP) * TQ + (qq - otq * TQ);
-          const unsigned long long* a =
-              xbuf + (size_t)((c - 1) & 1) * ntiles * (TP * TQ) + (size_t)(otp * g.ntq + otq) * (TP * TQ) + slot;
-          unsigned long long wv = ld64_relaxed(a);
-          unsigned long long polls = 0;
-          while ((unsigned)(wv >> 32) != epoch_in) {
-            if (ld_relaxed(words + kWordAbort) != 0u) {
-              fail = 1;
-              break;
-            }
-            if (++polls > limit) {
-              __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              fail = 1;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            wv = ld64_relaxed(a);
-          }
-          d0 = __uint_as_float((unsigned)wv);
-        }
-      }
-      // Cells outside the volume hold +inf in both planes, so candidates through
-      // them never win and the candidate loop needs no bounds checks.
-      P0[tid] = make_float2(d0, ix[0]);
-      if (!in) P1[tid] = make_float2(__builtin_inff(), 0.0f);
-      if (__syncthreads_or(fail)) return false;
-
-      // 3. The chunk's planes.
-      float2* Pp = P0;
-      float2* Pc = P1;
-      unsigned long long* xout = xbuf + (size_t)(c & 1) * ntiles * (TP * TQ) + (size_t)tile * (TP * TQ);
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        if (i >= kk) break;
-        if (in && e <= kk - 1 - i) {
-          const float ixj = ix[i + 1];
-          float best = g.init ? g.v * dd[i + 1] : dd[i + 1];
-          int choice = 0;
-#pragma unroll
-          for (int dp = -1; dp <= 1; ++dp) {
-#pragma unroll
-            for (int dq = -1; dq <= 1; ++dq) {
-              const int j = (dp + 1) * 3 + dq + 1;
-              const float2 y = Pp[tid + dp * BQ + dq];
-              const float cand = y.x + cell_edge<MODE>(g, j, ixj, y.y);
-              if (REC) {
-                if (cand < best) {
-                  best = cand;
-                  choice = 1 + j;
-                }
-              } else {
-                best = fminf(best, cand);
-              }
-            }
-          }
-          Pc[tid] = make_float2(best, ixj);
-          if (e == 0) {
-            const int x = xof(i + 1);
-            if (SCANC)
-              Res[own_slot * SCR + i] = best;
-            else
-              g.D[x] = best;
-            if (REC && g.rec) g.rec[x] = (uint8_t)choice;
-            if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
-          }
-        }
-        lds_barrier();
-        float2* t = Pp;
-        Pp = Pc;
-        Pc = t;
-      }
-
-      // 4. Scan-contiguous results: each own cell's kk planes as one run of
-      // consecutive memory positions, eight lanes per cell.
-      if (SCANC) {
-#pragma unroll
-        for (int f0 = 0; f0 < TP * TQ * K; f0 += NB) {
-          const int f = f0 + tid;
-          const int own = f / K, i = f - own * K;
-          const int opp = p0 + own / TQ, oqq = q0 + (own - (own / TQ) * TQ);
-          if (i < kk && opp < Np && oqq < Nq) {
-            const int t = t0 + i;
-            g.D[(g.sign > 0 ? t : Na - 1 - t) + opp * g.sp + oqq * g.sq] = Res[own * SCR + i];
-          }
-        }
-        // Res is rewritten only after the next staging barrier.
+    for (int j = 0; j <= K; ++j) {
+      const bool need = it.in && j <= it.kk && e <= it.kk - j;
+      nx[j] = 0.0f;
+      nd[j] = 0.0f;
+      if (need) {
+        const int x = xof(it, j);
+        if (USE_I) nx[j] = g.image[x];
+        if (j >= 1 || it.c == 0) nd[j] = dsrc0[x];
       }
     }
+  };
+  auto stage = [&](const Item& it) {
+    const int kb = run_start(it);
+    // the thread index, opaque to the optimiser: the staging index math is
+    // recomputed per item instead of being hoisted and held in registers
+    int stid = tid;
+    __asm__ volatile("" : "+v"(stid));
+    if (vec4s) {
+      constexpr int GPC = SC / 4;  // 16-byte groups per cell
+      constexpr int NG = STAGE / 4;
+#pragma unroll
+      for (int g0 = 0; g0 < NG; g0 += NB) {
+        const int gi = g0 + stid;
+        const int lx = gi / GPC, gg = gi - lx * GPC;
+        const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+        const int cpp = it.p0 - K + cbr, cqq = it.q0 - K + cbc;
+        const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+        const int k0 = kb + 4 * gg;
+        const bool ok = k0 + 3 <= Na - 1 && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+        // planes j held by this group, and the highest plane this cell needs
+        const int jlo = g.sign > 0 ? k0 - (it.t0 - 1) : (Na - it.t0) - (k0 + 3);
+        const int jtop = min(jlo + 3, it.kk - ce);
+        if (ok) {
+          const int x = k0 + cpp * g.sp + cqq * g.sq;
+          if (max(jlo, it.c == 0 ? 0 : 1) <= jtop)
+            __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + 4 * (g0 + wave0), 16, 0, 0);
+          if (USE_I && max(jlo, 0) <= jtop)
+            __builtin_amdgcn_global_load_lds(g.image + x, StI + 4 * (g0 + wave0), 16, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int f0 = 0; f0 < STAGE; f0 += NB) {
+        const int f = f0 + stid;
+        const int lx = f / SC, sl = f - lx * SC;
+        const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+        const int cpp = it.p0 - K + cbr, cqq = it.q0 - K + cbc;
+        const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+        const int k = kb + sl;
+        const int j = g.sign > 0 ? k - (it.t0 - 1) : (Na - it.t0) - k;
+        const bool ok = j >= 0 && j <= it.kk && ce <= it.kk - j && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+        if (ok) {
+          const int x = k + cpp * g.sp + cqq * g.sq;
+          if (j >= 1 || it.c == 0) __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + f0 + wave0, 4, 0, 0);
+          if (USE_I) __builtin_amdgcn_global_load_lds(g.image + x, StI + f0 + wave0, 4, 0, 0);
+        }
+      }
+    }
+  };
+
+  Item cur = item_of(0);
+  if (SCANC)
+    stage(cur);
+  else
+    fetch_regs(cur);
+  for (int n = 0; n < nitems; ++n) {
+    const int c = cur.c, kk = cur.kk;
+    const unsigned epoch_in = g.epoch_base + (unsigned)c;  // published by chunk c - 1
+    const unsigned epoch_out = epoch_in + 1u;
+    const bool has_next = n + 1 < nitems;
+    const Item nxt = item_of(has_next ? n + 1 : n);
+
+    // 1. This item's image and D_old.
+    float ix[K + 1], dd[K + 1];
+    if (SCANC) {
+      __builtin_amdgcn_s_waitcnt(0);  // the global->LDS copies have landed
+      __syncthreads();
+      const int sbase = slot_base(cur, run_start(cur));
+#pragma unroll
+      for (int j = 0; j <= K; ++j) {
+        const bool need = cur.in && j <= kk && e <= kk - j;
+        const int sl = tid * SC + sbase + g.sign * j;
+        ix[j] = (USE_I && need) ? StI[sl] : 0.0f;
+        dd[j] = (need && (j >= 1 || c == 0)) ? StD[sl] : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j <= K; ++j) {
+        ix[j] = nx[j];
+        dd[j] = nd[j];
+      }
+      if (has_next) fetch_regs(nxt);
+    }
+
+    // 2. Plane 0 of the chunk: the pass's first plane in chunk 0, else the
+    // values the previous chunk published (this tile's and its neighbours').
+    float d0 = __builtin_inff();
+    int fail = 0;
+    if (cur.in && e <= kk) {
+      if (c == 0) {
+        d0 = g.init ? g.v * dd[0] : dd[0];
+      } else {
+        const int otp = cur.pp / TP, otq = cur.qq / TQ;
+        const int slot = (cur.pp - otp * TP) * TQ + (cur.qq - otq * TQ);
+        const unsigned long long* a =
+            xbuf + (size_t)((c - 1) & 1) * ntiles * (TP * TQ) + (size_t)(otp * g.ntq + otq) * (TP * TQ) + slot;
+        unsigned long long wv = ld64_relaxed(a);
+        unsigned long long polls = 0;
+        while ((unsigned)(wv >> 32) != epoch_in) {
+          if (ld_relaxed(words + kWordAbort) != 0u) {
+            fail = 1;
+            break;
+          }
+          if (++polls > limit) {
+            __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            fail = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          wv = ld64_relaxed(a);
+        }
+        d0 = __uint_as_float((unsigned)wv);
+      }
+    }
+    // Cells outside the volume hold +inf in both planes, so candidates through
+    // them never win and the candidate loop needs no bounds checks.
+    P0[tid] = make_float2(d0, ix[0]);
+    if (!cur.in) P1[tid] = make_float2(__builtin_inff(), 0.0f);
+    if (__syncthreads_or(fail)) return false;
+    // every thread has copied its staged values: refill the staging area
+    if (SCANC && has_next) stage(nxt);
+
+    // 3. The chunk's planes.
+    float2* Pp = P0;
+    float2* Pc = P1;
+    unsigned long long* xout = xbuf + (size_t)(c & 1) * ntiles * (TP * TQ) + (size_t)cur.tile * (TP * TQ);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (i >= kk) break;
+      if (cur.in && e <= kk - 1 - i) {
+        const float ixj = ix[i + 1];
+        float best = g.init ? g.v * dd[i + 1] : dd[i + 1];
+        int choice = 0;
+#pragma unroll
+        for (int dp = -1; dp <= 1; ++dp) {
+#pragma unroll
+          for (int dq = -1; dq <= 1; ++dq) {
+            const int j = (dp + 1) * 3 + dq + 1;
+            const float2 y = Pp[tid + dp * BQ + dq];
+            const float cand = y.x + cell_edge<MODE>(g, j, ixj, y.y);
+            if (REC) {
+              if (cand < best) {
+                best = cand;
+                choice = 1 + j;
+              }
+            } else {
+              best = fminf(best, cand);
+            }
+          }
+        }
+        Pc[tid] = make_float2(best, ixj);
+        if (e == 0) {
+          const int x = xof(cur, i + 1);
+          if (SCANC)
+            Res[own_slot * SCR + i] = best;
+          else
+            g.D[x] = best;
+          if (REC && g.rec) g.rec[x] = (uint8_t)choice;
+          if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
+        }
+      }
+      lds_barrier();
+      float2* t = Pp;
+      Pp = Pc;
+      Pc = t;
+    }
+
+    // 4. Scan-contiguous results: each own cell's kk planes as one run of
+    // consecutive memory positions, eight lanes per cell.
+    if (SCANC) {
+#pragma unroll
+      for (int f0 = 0; f0 < TP * TQ * K; f0 += NB) {
+        const int f = f0 + tid;
+        const int own = f / K, i = f - own * K;
+        const int opp = cur.p0 + own / TQ, oqq = cur.q0 + (own - (own / TQ) * TQ);
+        if (i < kk && opp < Np && oqq < Nq) {
+          const int t = cur.t0 + i;
+          g.D[(g.sign > 0 ? t : Na - 1 - t) + opp * g.sp + oqq * g.sq] = Res[own * SCR + i];
+        }
+      }
+      // Res is rewritten only after the next item's staging barrier.
+    }
+    cur = nxt;
   }
   return true;
 }
