@@ -21,7 +21,17 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* wo
 template <bool SCANC, int RMODE, bool REC>
 __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, unsigned* words,
                                                                  unsigned long long limit) {
-  extern __shared__ float lds[];
+  __shared__ float2 pair[2 * kCellThreads];
+  __shared__ int fail;
+  CellLds lds{pair, nullptr, nullptr, nullptr, &fail};
+  if constexpr (SCANC) {
+    __shared__ float stD[kCellStage];
+    __shared__ float stI[kCellStage];
+    __shared__ float res[kCellTP * kCellTQ * kCellSCR];
+    lds.stD = stD;
+    lds.stI = stI;
+    lds.res = res;
+  }
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   run_pass_cell_mode<SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
                                         xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
@@ -164,12 +174,11 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
                        hipStream_t stream) {
   if (use_cell_path(d, ndim)) {
     PassKernel fn = select_cell_kernel(d);
-    const size_t lds = cell_lds_bytes(d.sa == 1);
-    const int cap = capacity_for(fn, lds, kCellThreads);
+    const int cap = capacity_for(fn, 0, kCellThreads);
     if (cap <= 0) return hipErrorInvalidConfiguration;
     const int ntiles = d.ntp * d.ntq;
     const int grid = ntiles < cap ? ntiles : cap;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), lds, stream, d, words, spin_limit);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), 0, stream, d, words, spin_limit);
     return hipGetLastError();
   }
   PassKernel fn = select_kernel(d, ndim);

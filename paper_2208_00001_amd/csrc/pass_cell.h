@@ -28,12 +28,6 @@ constexpr int kCellThreads = kCellBQ * kCellBQ;         // 1024: one thread per 
 constexpr int kCellSC = 4 * ((kCellK + 4 + 3) / 4);    // 12
 constexpr int kCellSCR = kCellK + 1;                     // 9
 constexpr int kCellStage = kCellThreads * kCellSC;       // floats of one staged array
-// LDS bytes: two (D, I) pair planes; with the scan axis contiguous also the staged
-// D_old and image runs and the results.
-constexpr size_t cell_lds_bytes(bool scanc) {
-  return sizeof(float) * ((size_t)4 * kCellThreads +
-                          (scanc ? (size_t)2 * kCellStage + (size_t)kCellTP * kCellTQ * kCellSCR : 0));
-}
 
 template <int MODE>
 __device__ __forceinline__ float cell_edge(const PassDesc& g, int j, float ix, float iy) {
@@ -48,9 +42,31 @@ __device__ __forceinline__ float cell_edge(const PassDesc& g, int j, float ix, f
 // axis is the contiguous memory axis; a thread's planes are then consecutive
 // floats, and are gathered through LDS by 16-byte runs instead of one load per
 // lane and plane.  False if a bounded wait gave up.
+// Workgroup barrier for the step loop: this wave's LDS accesses are complete
+// (lgkmcnt(0)) and the compiler moves no memory access across it.  Unlike a
+// release fence it does not wait for global stores or for global->LDS copies
+// in flight, which target other LDS arrays and are waited for where read.
+__device__ __forceinline__ void step_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt and expcnt at their maxima, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// LDS of the pass, as separate arrays: the global->LDS copies of the next item
+// then provably do not alias the pair planes, and the steps need not wait for
+// them to land.
+struct CellLds {
+  float2* pair;  // 2 x kCellThreads
+  float* stD;    // kCellStage (scan-contiguous layout only)
+  float* stI;    // kCellStage
+  float* res;    // kCellTP * kCellTQ * kCellSCR
+  int* fail;     // one word: item number + 1 of a bounded wait that gave up
+};
+
 template <bool SCANC, int MODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
-                                              unsigned long long limit, float* lds, int wg, int G) {
+                                              unsigned long long limit, const CellLds& lds, int wg, int G) {
   constexpr int TP = kCellTP, TQ = kCellTQ, K = kCellK, BQ = kCellBQ, NB = kCellThreads;
   constexpr int SC = kCellSC, SCR = kCellSCR, STAGE = kCellStage;
   const PassDesc g = *gp;
@@ -62,11 +78,11 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   const int ntiles = g.ntp * g.ntq;
   const int Na = g.Na, Np = g.Np, Nq = g.Nq;
   constexpr bool USE_I = MODE != kModeLam0;
-  float2* const P0 = reinterpret_cast<float2*>(lds);
+  float2* const P0 = lds.pair;
   float2* const P1 = P0 + NB;
-  float* const StD = lds + 4 * NB;  // SCANC only
-  float* const StI = StD + STAGE;
-  float* const Res = StI + STAGE;
+  float* const StD = lds.stD;
+  float* const StI = lds.stI;
+  float* const Res = lds.res;
   const int wave0 = tid & ~63;
   // 16-byte runs need every run start 16-byte aligned
   const bool vec4s = SCANC && (Na & 3) == 0 && (g.sp & 3) == 0 && (g.sq & 3) == 0;
@@ -86,7 +102,9 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     }
   }
 
+  if (tid == 0) *lds.fail = 0;  // read only after a barrier
   const float* const dsrc0 = g.init ? g.mask : g.D;
+  const float vscale = g.init ? g.v : 1.0f;
   // Work items in order: chunk-major, then this workgroup's tiles.  The next
   // item's image and D_old are fetched while the current item's planes are
   // advanced (into registers, or into the LDS staging area once the current
@@ -221,8 +239,10 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         ix[j] = nx[j];
         dd[j] = nd[j];
       }
-      if (has_next) fetch_regs(nxt);
     }
+    // The initialising pass reads the mask: D_old = v * M (1 * x == x otherwise).
+#pragma unroll
+    for (int j = 0; j <= K; ++j) dd[j] *= vscale;
 
     // 2. Plane 0 of the chunk: the pass's first plane in chunk 0, else the
     // values the previous chunk published (this tile's and its neighbours').
@@ -230,7 +250,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     int fail = 0;
     if (cur.in && e <= kk) {
       if (c == 0) {
-        d0 = g.init ? g.v * dd[0] : dd[0];
+        d0 = dd[0];
       } else {
         const int otp = cur.pp / TP, otq = cur.qq / TQ;
         const int slot = (cur.pp - otp * TP) * TQ + (cur.qq - otq * TQ);
@@ -239,14 +259,17 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         unsigned long long wv = ld64_relaxed(a);
         unsigned long long polls = 0;
         while ((unsigned)(wv >> 32) != epoch_in) {
-          if (ld_relaxed(words + kWordAbort) != 0u) {
-            fail = 1;
-            break;
-          }
-          if (++polls > limit) {
-            __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            fail = 1;
-            break;
+          // the abort word costs a memory round trip: look at it every 32 polls
+          if ((++polls & 31u) == 0u) {
+            if (ld_relaxed(words + kWordAbort) != 0u) {
+              fail = 1;
+              break;
+            }
+            if (polls > limit) {
+              __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              fail = 1;
+              break;
+            }
           }
           __builtin_amdgcn_s_sleep(1);
           wv = ld64_relaxed(a);
@@ -258,9 +281,18 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     // them never win and the candidate loop needs no bounds checks.
     P0[tid] = make_float2(d0, ix[0]);
     if (!cur.in) P1[tid] = make_float2(__builtin_inff(), 0.0f);
-    if (__syncthreads_or(fail)) return false;
-    // every thread has copied its staged values: refill the staging area
-    if (SCANC && has_next) stage(nxt);
+    if (fail) *lds.fail = n + 1;
+    step_barrier();
+    if (*lds.fail == n + 1) return false;
+    // Fetch the next item now: its loads overlap the steps, and nothing before
+    // this point waits on them.  With the scan axis contiguous every thread has
+    // copied its staged values, so the staging area can be refilled.
+    if (has_next) {
+      if (SCANC)
+        stage(nxt);
+      else
+        fetch_regs(nxt);
+    }
 
     // 3. The chunk's planes.
     float2* Pp = P0;
@@ -271,7 +303,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
       if (i >= kk) break;
       if (cur.in && e <= kk - 1 - i) {
         const float ixj = ix[i + 1];
-        float best = g.init ? g.v * dd[i + 1] : dd[i + 1];
+        float best = dd[i + 1];
         int choice = 0;
 #pragma unroll
         for (int dp = -1; dp <= 1; ++dp) {
@@ -301,7 +333,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
           if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
         }
       }
-      lds_barrier();
+      step_barrier();
       float2* t = Pp;
       Pp = Pc;
       Pc = t;
@@ -331,8 +363,8 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
 // classification word rules the fast edge cost out.
 template <bool SCANC, int RMODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
-                                                   const unsigned* cls_word, unsigned long long limit, float* lds,
-                                                   int wg, int G) {
+                                                   const unsigned* cls_word, unsigned long long limit,
+                                                   const CellLds& lds, int wg, int G) {
   if (RMODE == kModeGeneral) return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
