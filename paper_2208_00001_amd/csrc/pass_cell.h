@@ -284,15 +284,11 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     if (fail) *lds.fail = n + 1;
     step_barrier();
     if (*lds.fail == n + 1) return false;
-    // Fetch the next item now: its loads overlap the steps, and nothing before
-    // this point waits on them.  With the scan axis contiguous every thread has
-    // copied its staged values, so the staging area can be refilled.
-    if (has_next) {
-      if (SCANC)
-        stage(nxt);
-      else
-        fetch_regs(nxt);
-    }
+    // Fetch the next item's registers now: the loads overlap the steps, and
+    // nothing before this point waits on them.  (The scan-contiguous staging is
+    // refilled after the steps instead: global->LDS copies in flight slow the
+    // step loop down by more than their latency costs when exposed.)
+    if (!SCANC && has_next) fetch_regs(nxt);
 
     // 3. The chunk's planes.
     float2* Pp = P0;
@@ -325,6 +321,8 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         Pc[tid] = make_float2(best, ixj);
         if (e == 0) {
           const int x = xof(cur, i + 1);
+          // per-step stores spread over the steps' barrier stalls; the
+          // scan-contiguous layout stages its results for run-wise writes
           if (SCANC)
             Res[own_slot * SCR + i] = best;
           else
@@ -353,6 +351,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         }
       }
       // Res is rewritten only after the next item's staging barrier.
+      if (has_next) stage(nxt);
     }
     cur = nxt;
   }
