@@ -16,8 +16,10 @@ Also reported (same JSON line):
   roofline      the directional-pass kernel's algorithmic bytes (12 B per voxel
                 update: read I(x), read D_old(x), write D(x)) per launch over its
                 average launch duration, timed with HIP events on its stream,
-                against the MI355X HBM peak (8 TB/s); traffic from rocprofv3
-                counters when a summary for the current kernel source exists
+                against the MI355X HBM peak (8 TB/s) and against the measured rate
+                of a streaming kernel on 2 GiB; traffic from rocprofv3 counters
+                when a summary for the current kernel source exists
+  configs_2d    the 128^2 and 2048^2 x 3 images, voxel-updates/s per lambda
   cpu_baseline  the CPU oracle (single thread) on a bounded sample: one
                 iteration (6 passes) of the same volume
 
@@ -27,7 +29,6 @@ from __future__ import annotations
 
 import argparse
 import hashlib
-import glob
 import json
 import os
 import sys
@@ -42,11 +43,17 @@ BYTES_PER_VU = 12  # lambda = 1, C = 1: image(x) 4 + D_old(x) 4 + D(x) 4
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pass_kernel_3d_256_pmc.json")
 
 
+# Sources that define and launch the forward pass kernels and the scale kernel
+# the counters are calibrated with: a change to any of them makes the stored
+# counter summary stale.
+PASS_KERNEL_SOURCES = ("forward.hip", "ggdt_internal.h", "pass_cell.h", "pass_device.h")
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2208_00001_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
+    for name in PASS_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2208_00001_amd", "csrc", name), "rb") as f:
+            h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()
 
@@ -92,6 +99,61 @@ def calibrate_copy(mib):
     torch.cuda.synchronize()
     assert torch.equal(dst, src * 2.0)
     return {"kernel": "scale_kernel", "bytes_read": 4 * n, "bytes_written": 4 * n}
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """GB/s of the library's streaming scale kernel (read 4 B + write 4 B per
+    element) over a buffer larger than the 256 MB memory-side cache: the
+    achievable HBM rate that the pass kernel's algorithmic rate is compared to."""
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+
+    dev = "cuda:0"
+    plane = 512 * 512
+    n = gib * 2**30 // 4 // plane * plane
+    shape = (n // plane, 512, 512)
+    src = torch.ones(shape, device=dev)
+    dst = torch.empty(shape, device=dev)
+    ws = B.new_workspace(shape, 1, dev)
+
+    def run():
+        B.ggdt3d(src, src, (1.0, 1.0, 1.0), 1.0, 1.0, 0, out=dst, workspace=ws)
+
+    run()
+    ms = _time(run, reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "scale_kernel (D = v*M)", "bytes": 8 * n, "ms": ms, "gbs": 8 * n / (ms * 1e-3) / 1e9}
+
+
+def bench_small_configs(reps=5):
+    """Voxel-updates/s of the 2D configurations (reported, not targeted): the
+    128^2 correctness case and the 2048^2 x 3-channel case, per lambda."""
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd import synth
+
+    dev = "cuda:0"
+    res = {}
+    for name, cases in (("2d-128^2-c1", [synth.config1(lam) for lam in (0.0, 1.0)]),
+                        ("2d-2048^2-c3", [synth.config2(lam) for lam in (0.0, 0.5, 1.0)])):
+        for c in cases:
+            img = torch.from_numpy(c["image"]).to(dev)
+            m = torch.from_numpy(c["mask"]).to(dev)
+            out = torch.empty_like(m)
+            ws = B.new_workspace(tuple(m.shape), img.shape[0] if img.dim() > m.dim() else 1, dev)
+
+            def run():
+                B.ggdt2d(img, m, c["spacing"], c["v"], c["lam"], c["iterations"], out=out, workspace=ws)
+
+            run()
+            ms = _time(run, reps)
+            vu = int(np.prod(m.shape)) * 4 * c["iterations"]
+            res[f"{name}-lam{c['lam']:g}"] = {"ms": ms, "value": vu / (ms * 1e-3), "unit": "voxel-updates/s"}
+    return res
 
 
 def _time(fn, reps):
@@ -250,6 +312,8 @@ def main():
     achieved = BYTES_PER_VU * N / (avg_ms * 1e-3) / 1e9
     traffic = traffic_from_counters(N)
 
+    copy = copy_bandwidth()
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -268,10 +332,12 @@ def main():
                    "voxel_updates_per_step": vu_per_step, "seed": c["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "copy_gbs": copy["gbs"], "frac_of_copy": achieved / copy["gbs"],
                      "kernel": "directional pass (3D, lambda=1 C=1 path)", "bytes_per_voxel_update": BYTES_PER_VU,
                      "launches_timed": len(durs), "avg_launch_ms": avg_ms},
     }
     if not args.no_batched:
+        line["configs_2d"] = bench_small_configs()
         line["batched"] = bench_batched(max(3, min(args.steps, 10)))
         line["backward"] = bench_backward(max(3, min(args.steps, 10)))
     if args.calibrate_copy > 0:

@@ -128,9 +128,21 @@ __global__ __launch_bounds__(256) void classify_kernel(const float* img, long lo
                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void scale_kernel(const float* mask, float v, float* out, long long n) {
+// out = v * mask, 16 bytes per thread and iteration when both arrays are
+// 16-byte aligned (a plain streaming kernel; also the reference for the
+// achievable HBM rate).
+__global__ __launch_bounds__(256) void scale_kernel(const float* mask, float v, float* out, long long n) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = v * mask[i];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool vec = ((reinterpret_cast<uintptr_t>(mask) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+  const long long n4 = vec ? n / 4 : 0;
+  const float4* m4 = reinterpret_cast<const float4*>(mask);
+  float4* o4 = reinterpret_cast<float4*>(out);
+  for (long long i = t; i < n4; i += stride) {
+    const float4 m = m4[i];
+    o4[i] = make_float4(v * m.x, v * m.y, v * m.z, v * m.w);
+  }
+  for (long long i = 4 * n4 + t; i < n; i += stride) out[i] = v * mask[i];
 }
 
 struct CapEntry {
@@ -210,8 +222,8 @@ hipError_t launch_classify(const float* image, long long n, unsigned* words, hip
 }
 
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream) {
-  long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  long long blocks = (n / 4 + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, mask, v, out, n);
   return hipGetLastError();
