@@ -6,6 +6,7 @@
 // meet at an instance-local barrier (release fence, counter, bounded wait,
 // acquire fence), so instances never wait for each other.  The launch is sized to
 // the co-resident capacity, which the bounded waits require.
+#include "pass_cell.h"
 #include "pass_device.h"
 
 namespace ggdt {
@@ -43,23 +44,29 @@ __device__ bool instance_barrier(unsigned* counter, unsigned target, unsigned* w
   return ok;
 }
 
+// Batched workgroups have kBatchThreads threads: single-channel 3D instances
+// (class 0, K = 8) run the thread-per-cell pass, the others the tile pass with
+// that many threads.
+constexpr int kBatchThreads = kCellThreads;
+
 template <int NDIM, int TP, int TQ, int K, bool REC>
 __device__ __forceinline__ bool run_pass_rt(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                             const unsigned* cls, int mode, unsigned long long limit, float* lds,
                                             int wg, int G) {
+  constexpr int NT = kBatchThreads;
   const bool scanc = gp->sa == 1;
   if (scanc) {
-    if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam0, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
-    if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam1C1, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
-    return run_pass_mode<NDIM, TP, TQ, K, true, kModeGeneral, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+    if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam0, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
+    if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, true, kModeLam1C1, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
+    return run_pass_mode<NDIM, TP, TQ, K, true, kModeGeneral, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
   }
-  if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam0, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
-  if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam1C1, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
-  return run_pass_mode<NDIM, TP, TQ, K, false, kModeGeneral, REC>(gp, xbuf, words, cls, limit, lds, wg, G);
+  if (mode == kModeLam0) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam0, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
+  if (mode == kModeLam1C1) return run_pass_mode<NDIM, TP, TQ, K, false, kModeLam1C1, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
+  return run_pass_mode<NDIM, TP, TQ, K, false, kModeGeneral, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
 }
 
 template <int K3, int K2, bool REC>
-__global__ __launch_bounds__(kThreads) void batched_kernel(const BatchInst* __restrict__ insts, int ninst,
+__global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                            const PassDesc* __restrict__ passes, unsigned char* ws,
                                                            unsigned long long limit) {
   extern __shared__ float lds[];
@@ -81,10 +88,14 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(const BatchInst* __re
   for (int p = 0; p < in.npass; ++p) {
     const PassDesc* gp = passes + in.pass0 + p;
     bool ok;
-    if (in.ndim == 3)
-      ok = run_pass_rt<3, kTP3, kTQ3, K3, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
-    else
+    if (in.ndim == 3) {
+      if constexpr (K3 == kCellK)
+        ok = run_pass_cell_rt<REC>(gp, xbuf, words, cls, in.mode, limit, carve_cell_lds(lds), wg, in.nwg);
+      else
+        ok = run_pass_rt<3, kTP3, kTQ3, K3, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
+    } else {
       ok = run_pass_rt<2, 1, kTQ2, K2, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
+    }
     if (!ok) return;
     if (p + 1 < in.npass && !instance_barrier(ctr, (unsigned)(p + 1) * (unsigned)in.nwg, words, limit)) return;
   }
@@ -124,8 +135,12 @@ template <int K3, int K2>
 size_t lds_for(int C, bool has2d, bool has3d) {
   size_t b = 0;
   if (has3d) {
-    b = max(b, Layout<3, kTP3, kTQ3, K3, true>::bytes(C));
-    b = max(b, Layout<3, kTP3, kTQ3, K3, false>::bytes(C));
+    if (K3 == kCellK) {
+      b = max(b, kCellLdsBytes);
+    } else {
+      b = max(b, Layout<3, kTP3, kTQ3, K3, true>::bytes(C));
+      b = max(b, Layout<3, kTP3, kTQ3, K3, false>::bytes(C));
+    }
   }
   if (has2d) {
     b = max(b, Layout<2, 1, kTQ2, K2, true>::bytes(C));
@@ -148,14 +163,15 @@ int batched_capacity(int kclass, bool rec, size_t lds) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kThreads, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBatchThreads, lds) != hipSuccess)
+    return 0;
   return per_cu * cus;
 }
 
 hipError_t launch_batched(int kclass, bool rec, const BatchInst* insts, int ninst, const PassDesc* passes,
                           unsigned char* ws, int grid, size_t lds, unsigned long long spin_limit, hipStream_t stream) {
   BatchedKernel fn = pick(kclass, rec);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, stream, insts, ninst, passes, ws, spin_limit);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kBatchThreads), lds, stream, insts, ninst, passes, ws, spin_limit);
   return hipGetLastError();
 }
 

@@ -64,6 +64,23 @@ struct CellLds {
   int* fail;     // one word: item number + 1 of a bounded wait that gave up
 };
 
+// Bytes of one dynamic LDS area holding every array of CellLds.
+constexpr size_t kCellLdsBytes = sizeof(float2) * 2 * kCellThreads +
+                                 sizeof(float) * ((size_t)2 * kCellStage + (size_t)kCellTP * kCellTQ * kCellSCR) +
+                                 sizeof(int);
+
+// CellLds carved from one dynamic LDS area of kCellLdsBytes (launches that
+// share the area with other paths).
+__device__ __forceinline__ CellLds carve_cell_lds(float* lds) {
+  CellLds l;
+  l.pair = reinterpret_cast<float2*>(lds);
+  l.stD = lds + 4 * kCellThreads;
+  l.stI = l.stD + kCellStage;
+  l.res = l.stI + kCellStage;
+  l.fail = reinterpret_cast<int*>(l.res + kCellTP * kCellTQ * kCellSCR);
+  return l;
+}
+
 template <bool SCANC, int MODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                               unsigned long long limit, const CellLds& lds, int wg, int G) {
@@ -76,6 +93,8 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   const int e = max(max(max(K - br, br - (K + TP - 1)), max(K - bc, bc - (K + TQ - 1))), 0);
   const int own_slot = (br - K) * TQ + (bc - K);  // valid when e == 0
   const int ntiles = g.ntp * g.ntq;
+  // A batched instance may hold more workgroups than this pass has tiles.
+  if (wg >= ntiles) return true;
   const int Na = g.Na, Np = g.Np, Nq = g.Nq;
   constexpr bool USE_I = MODE != kModeLam0;
   float2* const P0 = lds.pair;
@@ -109,7 +128,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   // item's image and D_old are fetched while the current item's planes are
   // advanced (into registers, or into the LDS staging area once the current
   // item has copied its values out of it).
-  const int nmine = (ntiles - wg + G - 1) / G;  // grid <= ntiles, so >= 1
+  const int nmine = (ntiles - wg + G - 1) / G;  // >= 1 since wg < ntiles
   const int nitems = g.nchunk * nmine;
   struct Item {
     int c, t0, kk, tile, p0, q0, pp, qq, xpq;
@@ -369,6 +388,21 @@ __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned 
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
   if (fast) return run_pass_cell<SCANC, RMODE, REC>(gp, xbuf, words, limit, lds, wg, G);
   return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
+}
+
+// Layout and requested mode chosen at run time (batched launches).
+template <bool REC>
+__device__ __forceinline__ bool run_pass_cell_rt(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
+                                                 const unsigned* cls_word, int mode, unsigned long long limit,
+                                                 const CellLds& lds, int wg, int G) {
+  if (gp->sa == 1) {
+    if (mode == kModeLam0) return run_pass_cell_mode<true, kModeLam0, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
+    if (mode == kModeLam1C1) return run_pass_cell_mode<true, kModeLam1C1, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
+    return run_pass_cell_mode<true, kModeGeneral, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
+  }
+  if (mode == kModeLam0) return run_pass_cell_mode<false, kModeLam0, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
+  if (mode == kModeLam1C1) return run_pass_cell_mode<false, kModeLam1C1, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
+  return run_pass_cell_mode<false, kModeGeneral, REC>(gp, xbuf, words, cls_word, limit, lds, wg, G);
 }
 
 }  // namespace dev

@@ -95,7 +95,7 @@ __device__ __forceinline__ float edge_cost(const PassDesc& g, int j, float ix0, 
 
 // One directional pass of one instance, run by workgroup `wg` of the G
 // workgroups given to the instance.  Returns false if a bounded wait gave up.
-template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE, bool REC>
+template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE, bool REC, int NT = kThreads>
 __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                          unsigned long long limit, float* lds, int wg, int G) {
   const PassDesc g = *gp;  // uniform copy: no aliasing with the stores below
@@ -127,7 +127,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       const int tp = tile / g.ntq, tq = tile - tp * g.ntq;
       const int p0 = tp * TP, q0 = tq * TQ;
       const int rp = min(TP, Np - p0), rq = min(TQ, Nq - q0);
-      for (int f = tid; f < rp * rq; f += kThreads) {
+      for (int f = tid; f < rp * rq; f += NT) {
         const int r = f / rq, cq = f - r * rq;
         const int x = kf * g.sa + (p0 + r) * g.sp + (q0 + cq) * g.sq;
         if (g.init) g.D[x] = g.v * g.mask[x];
@@ -153,6 +153,11 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       const int p0 = tp * TP, q0 = tq * TQ;
       const int bp0 = (NDIM == 3) ? p0 - K : 0;
       const int bq0 = q0 - K;
+      // the thread index, opaque to the optimiser: per-thread index math of the
+      // unrolled loops below is recomputed per tile instead of being hoisted
+      // out of the chunk loop and held in registers for the whole pass
+      int tid = threadIdx.x;
+      __asm__ volatile("" : "+v"(tid));
 
       // 1. Global -> LDS copies of the chunk's planes.  Plane j is scan position
       // t0 - 1 + j.  Cell needed iff its distance outside the tile is <= kk - j.
@@ -165,7 +170,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
           // 16-byte groups of 4 cells along q (the contiguous axis): groups never
           // straddle the plane edge because q0 - K and Nq are multiples of 4.
           constexpr int NG = STAGE / 4;
-          for (int g0 = 0; g0 < NG; g0 += kThreads) {
+          for (int g0 = 0; g0 < NG; g0 += NT) {
             const int gi = g0 + tid;
             const int j = gi / (NB / 4);
             const int lx = 4 * (gi - j * (NB / 4));
@@ -189,7 +194,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
           // its end.
           constexpr int GPC = SC / 4;  // groups per cell
           constexpr int NG = STAGE / 4;
-          for (int g0 = 0; g0 < NG; g0 += kThreads) {
+          for (int g0 = 0; g0 < NG; g0 += NT) {
             const int gi = g0 + tid;
             const int lx = gi / GPC, gg = gi - lx * GPC;
             const int br = lx / BQ, bc = lx - br * BQ;
@@ -211,7 +216,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
             }
           }
         } else {
-          for (int f0 = 0; f0 < STAGE; f0 += kThreads) {
+          for (int f0 = 0; f0 < STAGE; f0 += NT) {
             const int f = f0 + tid;
             int j, lx, k;
             if (SCANC) {
@@ -242,7 +247,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
 
       // 2. The plane before the chunk on the tile grown by kk: exchange words of
       // the previous chunk (chunk 0: the staged first plane of the pass).
-      constexpr int MAXB = (NB + kThreads - 1) / kThreads;
+      constexpr int MAXB = (NB + NT - 1) / NT;
       unsigned long long wv[MAXB];
       int lxs[MAXB];
 #pragma unroll
@@ -251,7 +256,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
         const unsigned long long* xin = xbuf + (size_t)((c - 1) & 1) * ntiles * (TP * TQ);
 #pragma unroll
         for (int n = 0; n < MAXB; ++n) {
-          const int lx = tid + n * kThreads;
+          const int lx = tid + n * NT;
           const int br = lx / BQ, bc = lx - br * BQ;
           const int pp = bp0 + br, qq = bq0 + bc;
           bool ok = lx < NB && qq >= 0 && qq < Nq && (NDIM == 2 || (pp >= 0 && pp < Np));
@@ -299,7 +304,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       // needs no bounds checks.
 #pragma unroll
       for (int n = 0; n < MAXB; ++n) {
-        const int lx = tid + n * kThreads;
+        const int lx = tid + n * NT;
         if (lx >= NB) break;
         const int br = lx / BQ, bc = lx - br * BQ;
         const int pp = bp0 + br, qq = bq0 + bc;
@@ -333,15 +338,15 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
         const float inv_rq = 1.0f / (float)rq;
         // Up to U cells per thread in one block: all their LDS reads are issued
         // before any is consumed, so a plane costs about one LDS round trip.
-        constexpr int U = (NB + kThreads - 1) / kThreads;
-        const int nu = (cnt + kThreads - 1) / kThreads;  // uniform
+        constexpr int U = (NB + NT - 1) / NT;
+        const int nu = (cnt + NT - 1) / NT;  // uniform
         int lxs[U], pps[U], qqs[U];
         float dold[U], ix0[U];
         float2 nb[U][9];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (u >= nu) break;
-          const int f0 = tid + u * kThreads;
+          const int f0 = tid + u * NT;
           const int f = f0 < cnt ? f0 : cnt - 1;
           int r, cq;
           if (NDIM == 3) {
@@ -365,7 +370,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (u >= nu) break;
-          if (tid + u * kThreads >= cnt) continue;
+          if (tid + u * NT >= cnt) continue;
           const int lx = lxs[u], pp = pps[u], qq = qqs[u];
           float best = g.init ? g.v * dold[u] : dold[u];
           int choice = 0;
@@ -412,7 +417,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       if (SCANC) {
         const int rp = (NDIM == 3) ? min(TP, Np - p0) : 1;
         const int rq = min(TQ, Nq - q0);
-        for (int f = tid; f < TP * TQ * SCR; f += kThreads) {
+        for (int f = tid; f < TP * TQ * SCR; f += NT) {
           const int own = f / SCR, i = f - own * SCR;
           const int r = (NDIM == 3) ? own / TQ : 0, cq = own - r * TQ;
           if (i < kk && r < rp && cq < rq) {
@@ -430,16 +435,16 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
 
 // Requested mode RMODE falls back to the general formula when the image
 // classification word rules the fast edge cost out.
-template <int NDIM, int TP, int TQ, int K, bool SCANC, int RMODE, bool REC>
+template <int NDIM, int TP, int TQ, int K, bool SCANC, int RMODE, bool REC, int NT = kThreads>
 __device__ __forceinline__ bool run_pass_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                               const unsigned* cls_word, unsigned long long limit, float* lds, int wg,
                                               int G) {
   if (RMODE == kModeGeneral)
-    return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
+    return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
-  if (fast) return run_pass<NDIM, TP, TQ, K, SCANC, RMODE, REC>(gp, xbuf, words, limit, lds, wg, G);
-  return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
+  if (fast) return run_pass<NDIM, TP, TQ, K, SCANC, RMODE, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
+  return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
 }
 
 }  // namespace dev
