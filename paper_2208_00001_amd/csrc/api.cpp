@@ -171,6 +171,16 @@ void edge_constants(const Problem& pr, int axis, const float* spacing, float lam
   }
 }
 
+// The general edge cost's root argument fmaf(lambda, g, A_j) is at least A_j, so
+// with every A_j >= 2^-96 (and finite image values, checked on the device) it
+// lies in the normal range that sqrt_rn_normal handles.
+int sqrt_normal_for(const float* A, int ndim) {
+  const int nj = ndim == 3 ? 9 : 3;
+  float amin = A[0];
+  for (int j = 1; j < nj; ++j) amin = A[j] < amin ? A[j] : amin;
+  return amin >= 0x1p-96f ? 1 : 0;
+}
+
 int requested_mode(float lam, int C) {
   if (lam == 0.0f) return kModeLam0;
   if (lam == 1.0f && C == 1) return kModeLam1C1;
@@ -210,10 +220,8 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
     if (launch_scale(mask, v, out, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
     return GGDT_OK;
   }
-  const int mode = requested_mode(lam, pr.C);
-  if (mode != kModeGeneral) {
-    if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
-  }
+  // The image classification decides every pass's edge-cost mode on the device.
+  if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   unsigned base = 0;
   const int npass = iterations * 2 * pr.ndim;
   for (int p = 0; p < npass; ++p) {
@@ -257,6 +265,7 @@ int build_pass(const Problem& pr, const float* image, const float* mask, const f
   d->init = p == 0 ? 1 : 0;
   d->rec = records ? records + (size_t)p * pr.N : nullptr;
   d->epoch_base = epoch_base;
+  d->sqrt_normal = sqrt_normal_for(d->A, pr.ndim);
   return GGDT_OK;
 }
 

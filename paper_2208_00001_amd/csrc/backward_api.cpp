@@ -42,6 +42,7 @@ int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records
   d->ntq = f.ntq;
   d->nchunk = (f.Na - 1 + K - 1) / K;
   d->mode = f.mode;
+  d->sqrt_normal = f.sqrt_normal;
   d->lam = lam;
   for (int j = 0; j < 9; ++j) d->A[j] = f.A[j];
   d->epoch_base = epoch_base;
@@ -80,9 +81,7 @@ int backward_entry(int ndim, const int* dims, int C, const float* image, const u
   if (launch_reset(words, (long long)(fwd_ws / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (launch_reset((unsigned*)grad_image, (long long)pr.N * C, stream) != hipSuccess) return GGDT_ERR_HIP;
   if (iterations == 0) return launch_scale(grad_out, v, grad_softmask, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
-  if (requested_mode(lam, C) == kModeLam1C1 &&
-      launch_classify(image, (long long)C * pr.N, words, stream) != hipSuccess)
-    return GGDT_ERR_HIP;
+  if (launch_classify(image, (long long)C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   const int P = iterations * 2 * ndim;
   unsigned base = 0;
   const float* a_in = grad_out;

@@ -63,7 +63,7 @@ __device__ __forceinline__ float bwd_edge(const BwdDesc& g, int j, const float* 
     const float dc = sx[c * cstride] - sy[c * cstride];
     s = fmaf(dc, dc, s);
   }
-  return sqrtf(fmaf(g.lam, s, spatial_term(g, j)));
+  return general_root<MODE>(fmaf(g.lam, s, spatial_term(g, j)));
 }
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE>
@@ -85,7 +85,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
   const int ntiles = g.ntp * g.ntq;
   const int Np = g.Np, Nq = g.Nq, Na = g.Na;
   constexpr bool USE_I = MODE != kModeLam0;
-  const int nch = USE_I ? (MODE == kModeGeneral ? g.C : 1) : 0;
+  const int nch = USE_I ? ((MODE == kModeGeneral || MODE == kModeGeneralN) ? g.C : 1) : 0;
 
   // Last plane of the forward scan (never a parent plane): its own terms.
   {
@@ -118,7 +118,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
               const float dc = g.image[(long long)c * g.N + x] - g.image[(long long)c * g.N + y];
               s = fmaf(dc, dc, s);
             }
-            w = sqrtf(fmaf(g.lam, s, spatial_term(g, j)));
+            w = general_root<MODE>(fmaf(g.lam, s, spatial_term(g, j)));
           }
           if (w > 0.0f) {
             const float coef = (a * g.lam) / w;
@@ -404,6 +404,8 @@ __device__ __forceinline__ bool run_bwd_pass_mode(const BwdDesc* gp, unsigned lo
   if (mode == kModeLam0) return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam0>(gp, xbuf, words, limit, lds, wg, G);
   if (mode == kModeLam1C1 && ld_relaxed(cls_word) == 0u)
     return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam1C1>(gp, xbuf, words, limit, lds, wg, G);
+  if (mode == kModeGeneral && general_n_ok(gp->sqrt_normal, cls_word))
+    return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN>(gp, xbuf, words, limit, lds, wg, G);
   return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral>(gp, xbuf, words, limit, lds, wg, G);
 }
 

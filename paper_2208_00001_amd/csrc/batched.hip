@@ -107,7 +107,6 @@ __global__ __launch_bounds__(256) void batched_classify_kernel(const BatchInst* 
                                                                unsigned char* ws) {
   for (int i = 0; i < ninst; ++i) {
     const BatchInst in = insts[i];
-    if (in.mode == kModeGeneral) continue;  // uniform
     unsigned bits = 0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < in.nimg; t += stride) {

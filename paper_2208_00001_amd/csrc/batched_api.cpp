@@ -101,7 +101,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     has2d |= instances[i].ndim == 2;
     has3d |= instances[i].ndim == 3;
     rec |= instances[i].records != nullptr;
-    any_cls |= requested_mode(instances[i].lambda, instances[i].C) != kModeGeneral;
+    any_cls = true;  // the classification decides every instance's edge-cost mode
   }
   int kclass = maxC <= kBatchMaxC[0] ? 0 : 1;
   if (tuning && tuning->chunk > 0) {

@@ -24,6 +24,7 @@ enum Mode : int {
   kModeLam0 = 0,     // lambda == 0: w = sqrtf(A_j), a per-offset constant
   kModeLam1C1 = 1,   // lambda == 1 and C == 1: w = |I(x) - I(y)|
   kModeGeneral = 2,  // w = sqrtf(fmaf(lambda, g, A_j))
+  kModeGeneralN = 3, // the same, with the root's argument known to lie in [2^-96, FLT_MAX]
 };
 
 // LDS layout of the pass kernel for one tile geometry.  A chunk stages K + 1
@@ -71,6 +72,7 @@ struct PassDesc {
   float A[9];          // (float)((1 - lambda) * |dx|_s^2) per offset j
   float W0[9];         // sqrtf(A[j]), used when lambda == 0
   unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
+  int sqrt_normal;     // min_j A[j] >= 2^-96: the general root may use kModeGeneralN
 };
 
 // Reverse of one forward pass (see backward_device.h).  Geometry fields as in
@@ -96,6 +98,7 @@ struct BwdDesc {
   unsigned epoch_base;
   long long a_in_off;   // >= 0: a_in is at this byte offset of the workspace (batched scratch)
   long long a_out_off;  // >= 0: same for a_out
+  int sqrt_normal;      // as in PassDesc
 };
 
 // One instance of a batched launch (device-resident table).  Its passes are

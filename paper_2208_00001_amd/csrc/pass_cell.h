@@ -34,7 +34,7 @@ __device__ __forceinline__ float cell_edge(const PassDesc& g, int j, float ix, f
   if (MODE == kModeLam0) return g.W0[j];
   const float d = ix - iy;
   if (MODE == kModeLam1C1) return fabsf(d);
-  return sqrtf(fmaf(g.lam, d * d, g.A[j]));
+  return general_root<MODE>(fmaf(g.lam, d * d, g.A[j]));
 }
 
 // One pass of one single-channel 3D instance by workgroup `wg` of G (blockDim
@@ -383,7 +383,11 @@ template <bool SCANC, int RMODE, bool REC>
 __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                                    const unsigned* cls_word, unsigned long long limit,
                                                    const CellLds& lds, int wg, int G) {
-  if (RMODE == kModeGeneral) return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
+  if (RMODE == kModeGeneral) {
+    if (general_n_ok(gp->sqrt_normal, cls_word))
+      return run_pass_cell<SCANC, kModeGeneralN, REC>(gp, xbuf, words, limit, lds, wg, G);
+    return run_pass_cell<SCANC, kModeGeneral, REC>(gp, xbuf, words, limit, lds, wg, G);
+  }
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
   if (fast) return run_pass_cell<SCANC, RMODE, REC>(gp, xbuf, words, limit, lds, wg, G);

@@ -75,6 +75,34 @@ __device__ __forceinline__ int outside(int pp, int qq, int p0, int q0) {
   return max(dp, dq);
 }
 
+// Correctly rounded square root of x in [2^-96, FLT_MAX]: the hardware root
+// (within one ulp) corrected to the nearest by the signs of the residuals
+// x - (s -+ ulp) * s.  In this range it returns the bits of sqrtf as built
+// here (the correctly rounded lowering scales only arguments below 2^-96 and
+// special-cases only zero and infinity).
+__device__ __forceinline__ float sqrt_rn_normal(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float lo = __int_as_float(__float_as_int(s) - 1);
+  const float hi = __int_as_float(__float_as_int(s) + 1);
+  const float e_lo = fmaf(-lo, s, x);
+  const float e_hi = fmaf(-hi, s, x);
+  float r = e_lo <= 0.0f ? lo : s;
+  r = e_hi > 0.0f ? hi : r;
+  return r;
+}
+
+// sqrtf(x) for the general modes.
+template <int MODE>
+__device__ __forceinline__ float general_root(float x) {
+  return MODE == kModeGeneralN ? sqrt_rn_normal(x) : sqrtf(x);
+}
+
+// Mode for a pass whose requested mode RMODE is the general one: the
+// normal-range root when the spatial terms allow it and no image value is huge.
+__device__ __forceinline__ bool general_n_ok(int sqrt_normal, const unsigned* cls_word) {
+  return sqrt_normal != 0 && (ld_relaxed(cls_word) & kClassHuge) == 0u;
+}
+
 template <int MODE>
 __device__ __forceinline__ float edge_cost(const PassDesc& g, int j, float ix0, float iy0, const float* sx,
                                            const float* sy, int cstride) {
@@ -89,7 +117,7 @@ __device__ __forceinline__ float edge_cost(const PassDesc& g, int j, float ix0, 
       const float dc = sx[c * cstride] - sy[c * cstride];
       s = fmaf(dc, dc, s);
     }
-    return sqrtf(fmaf(g.lam, s, g.A[j]));
+    return general_root<MODE>(fmaf(g.lam, s, g.A[j]));
   }
 }
 
@@ -112,7 +140,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
   const int ntiles = g.ntp * g.ntq;
   const int Np = g.Np, Nq = g.Nq, Na = g.Na;
   const bool use_img = MODE != kModeLam0;
-  const int nch = MODE == kModeGeneral ? g.C : (use_img ? 1 : 0);
+  const int nch = (MODE == kModeGeneral || MODE == kModeGeneralN) ? g.C : (use_img ? 1 : 0);
   // 16-byte global->LDS copies need q contiguous and every row start 16-byte aligned.
   const bool vec4 = g.sq == 1 && (g.Nq & 3) == 0 && (g.sp & 3) == 0 && (g.sa & 3) == 0;
   // The same for the scan-contiguous layout: aligned runs along the scan axis.
@@ -439,8 +467,11 @@ template <int NDIM, int TP, int TQ, int K, bool SCANC, int RMODE, bool REC, int 
 __device__ __forceinline__ bool run_pass_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                               const unsigned* cls_word, unsigned long long limit, float* lds, int wg,
                                               int G) {
-  if (RMODE == kModeGeneral)
+  if (RMODE == kModeGeneral) {
+    if (general_n_ok(gp->sqrt_normal, cls_word))
+      return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
     return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
+  }
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
   if (fast) return run_pass<NDIM, TP, TQ, K, SCANC, RMODE, REC, NT>(gp, xbuf, words, limit, lds, wg, G);

@@ -90,6 +90,21 @@ def test_fast_path_fallback_on_extreme_values(scale, lam):
     check_case(c)
 
 
+@pytest.mark.parametrize("shape,C,lam,spacing", [((29, 35, 26), 1, 0.3, (1.0, 0.5, 2.0)),
+                                                  ((21, 30, 17), 2, 0.9, (0.25, 1.0, 1.0)),
+                                                  ((260, 190), 1, 0.6, (3.0, 0.5))])
+def test_general_root_over_wide_magnitudes(shape, C, lam, spacing):
+    """The general edge cost with image magnitudes log-uniform over [2^-40, 2^59]
+    (random signs): the root's argument then spans most of the fp32 exponent
+    range, which is where a shortened correctly rounded root would go wrong."""
+    c = synth.small_case(shape, C=C, seed=11, lam=lam, iterations=2, spacing=spacing)
+    rng = np.random.default_rng(11)
+    e = rng.uniform(-40.0, 59.0, size=c["image"].shape)
+    c["image"] = (np.sign(rng.uniform(-1, 1, size=e.shape)) * np.exp2(e)).astype(np.float32)
+    c["v"] = 1e30
+    check_case(c)
+
+
 @pytest.mark.parametrize("shape,C,lam", [((40, 37, 33), 1, 1.0), ((19, 50, 21), 2, 0.6), ((300, 270), 1, 0.0),
                                          ((270, 300), 3, 0.4)])
 def test_records_match_oracle(shape, C, lam):
