@@ -103,6 +103,30 @@ int ggdt3d_forward_rec(const float* image, const float* softmask, const float* s
                        float lambda, int iterations, float* out, uint8_t* records, int C, int D, int H,
                        int W, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Forward run to its fixed point.  The paper's transform repeats the directional
+ * passes for a given number of iterations (section "Implementation"); each
+ * iteration can only lower D, so repeating until an iteration changes nothing
+ * gives the converged transform, the exact shortest-path distance on the 8/26-
+ * connected grid with the same edge costs.  Runs whole iterations (same
+ * schedule and arithmetic as ggdt2d/ggdt3d) until one lowers no value, at most
+ * max_iterations (>= 0); arguments otherwise as ggdt2d/ggdt3d, same workspace
+ * size.  Asynchronous: the number of iterations comes from
+ * ggdt_workspace_iterations.  out then equals ggdt2d/ggdt3d with that many
+ * iterations (with max_iterations when it did not converge). */
+int ggdt2d_converge(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int max_iterations, float* out, int C, int H, int W, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+int ggdt3d_converge(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int max_iterations, float* out, int C, int D, int H, int W, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
+/* After a ggdt{2,3}d_converge call on `stream` with this workspace: synchronises
+ * the stream and stores in *iterations the number of iterations that lowered
+ * some value (the fixed point was confirmed by the next one), or -1 if
+ * max_iterations passed without reaching it.  GGDT_ERR_WATCHDOG if an
+ * inter-workgroup wait of the call expired. */
+int ggdt_workspace_iterations(const void* workspace, hipStream_t stream, int* iterations);
+
 /* Bytes of device workspace the backward entry points need: the forward's
  * workspace plus one fp32 adjoint buffer of prod(dims) values.  0 for invalid
  * shapes.  1 <= C <= 8 for the backward. */

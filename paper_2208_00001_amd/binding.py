@@ -57,6 +57,11 @@ _SIGS = {
                                  _vp, _c_size, _vp]),
     "ggdt3d_backward": (_c_int, [_vp, _vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _vp, _c_int, _c_int, _c_int,
                                  _c_int, _vp, _c_size, _vp]),
+    "ggdt2d_converge": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp,
+                                 _c_size, _vp]),
+    "ggdt3d_converge": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
+                                 _vp, _c_size, _vp]),
+    "ggdt_workspace_iterations": (_c_int, [_vp, _vp, _vp]),
     "ggdt_workspace_status": (_c_int, [_vp, _vp]),
     "ggdt_set_spin_limit": (None, [ctypes.c_ulonglong]),
     "ggdt_profile_begin": (_c_int, [_c_int]),
@@ -168,6 +173,29 @@ def ggdt3d(image, softmask, spacing=(1.0, 1.0, 1.0), v=1e10, lamb=1.0, iteration
     if softmask.dim() != 3:
         raise ValueError("softmask must be (D, H, W)")
     return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None)
+
+
+def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100, out=None, workspace=None):
+    """Forward run to its fixed point (2D or 3D by the mask's rank).  Returns
+    (D, iterations): the number of iterations that lowered some value, or -1 if
+    max_iterations passed without reaching the fixed point.  Synchronises."""
+    lib = load_library()
+    image, softmask, spatial = _prep(image, softmask)
+    nd, C = len(spatial), image.shape[0]
+    if out is None:
+        out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    if workspace is None:
+        workspace = new_workspace(spatial, C, softmask.device)
+    fn = lib.ggdt2d_converge if nd == 2 else lib.ggdt3d_converge
+    rc = fn(_ptr(image), _ptr(softmask), _spacing(spacing, nd), float(v), float(lamb), int(max_iterations),
+            _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    n = ctypes.c_int(0)
+    rc = lib.ggdt_workspace_iterations(_ptr(workspace), _stream(), ctypes.byref(n))
+    if rc != GGDT_OK:
+        raise GGDTError(rc, "ggdt_workspace_iterations")
+    return out, n.value
 
 
 def ggdt_forward_rec(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, records=None,

@@ -269,6 +269,47 @@ int build_pass(const Problem& pr, const float* image, const float* mask, const f
   return GGDT_OK;
 }
 
+// Convergence mode: up to max_iterations whole iterations, each followed by the
+// iteration-end kernel; passes after a no-change iteration return at once.
+int converge_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
+                   float v, float lam, int max_iterations, float* out, void* ws, size_t wsb, hipStream_t stream) {
+  if (!image || !mask || !out || !ws || !dims) return GGDT_ERR_NULL_PTR;
+  Problem pr;
+  int rc = make_problem(ndim, dims, C, &pr);
+  if (rc) return rc;
+  rc = check_params(ndim, spacing, v, lam, max_iterations);
+  if (rc) return rc;
+  const Tuning tu{};
+  if (wsb < workspace_for(pr, tu)) return GGDT_ERR_WORKSPACE_TOO_SMALL;
+  const size_t nb = (size_t)pr.N * 4, ni = (size_t)pr.N * pr.C * 4;
+  const void* ins[3] = {image, mask, ws};
+  const size_t nins[3] = {ni, nb, wsb};
+  rc = check_alias(out, nb, ins, nins, 3);
+  if (rc) return rc;
+  rc = check_device();
+  if (rc) return rc;
+  unsigned* words = (unsigned*)ws;
+  unsigned long long* xbuf = (unsigned long long*)(words + kHeaderWords);
+  if (launch_reset(words, (long long)(workspace_for(pr, tu) / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (max_iterations == 0) return launch_scale(mask, v, out, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
+  if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  unsigned base = 0;
+  const int per = 2 * pr.ndim;
+  for (int it = 1; it <= max_iterations; ++it) {
+    for (int k = 0; k < per; ++k) {
+      PassDesc d;
+      rc = build_pass(pr, image, mask, spacing, v, lam, out, nullptr, (it - 1) * per + k, base, &d);
+      if (rc) return rc;
+      d.xbuf = xbuf;
+      d.converge = 1;
+      base += (unsigned)d.nchunk + 1u;
+      if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+    }
+    if (launch_iteration_end(words, it, stream) != hipSuccess) return GGDT_ERR_HIP;
+  }
+  return GGDT_OK;
+}
+
 int forward_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
                   float v, float lam, int iterations, float* out, uint8_t* records, bool want_records, void* ws,
                   size_t wsb, hipStream_t stream) {
@@ -349,6 +390,32 @@ int ggdt3d_forward_rec(const float* image, const float* softmask, const float* s
   const int dims[3] = {D, H, W};
   return forward_entry(3, dims, C, image, softmask, spacing, v, lambda, iterations, out, records, true, workspace,
                        workspace_bytes, stream);
+}
+
+int ggdt2d_converge(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int max_iterations, float* out, int C, int H, int W, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream) {
+  const int dims[2] = {H, W};
+  return converge_entry(2, dims, C, image, softmask, spacing, v, lambda, max_iterations, out, workspace,
+                        workspace_bytes, stream);
+}
+
+int ggdt3d_converge(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int max_iterations, float* out, int C, int D, int H, int W, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream) {
+  const int dims[3] = {D, H, W};
+  return converge_entry(3, dims, C, image, softmask, spacing, v, lambda, max_iterations, out, workspace,
+                        workspace_bytes, stream);
+}
+
+int ggdt_workspace_iterations(const void* workspace, hipStream_t stream, int* iterations) {
+  if (!workspace || !iterations) return GGDT_ERR_NULL_PTR;
+  if (hipStreamSynchronize(stream) != hipSuccess) return GGDT_ERR_HIP;
+  unsigned w[kWordIters + 1] = {0};
+  if (hipMemcpy(w, workspace, sizeof w, hipMemcpyDeviceToHost) != hipSuccess) return GGDT_ERR_HIP;
+  if (w[kWordAbort]) return GGDT_ERR_WATCHDOG;
+  *iterations = w[kWordDone] ? (int)w[kWordIters] : -1;
+  return GGDT_OK;
 }
 
 int ggdt_workspace_status(const void* workspace, hipStream_t stream) {

@@ -13,6 +13,7 @@ template <int NDIM, int TP, int TQ, int K, bool SCANC, int RMODE, bool REC>
 __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* words, unsigned long long limit) {
   extern __shared__ float lds[];
   if (ld_relaxed(words + kWordAbort) != 0u) return;
+  if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
   run_pass_mode<NDIM, TP, TQ, K, SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
                                                     xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
@@ -33,6 +34,7 @@ __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, uns
     lds.res = res;
   }
   if (ld_relaxed(words + kWordAbort) != 0u) return;
+  if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
   run_pass_cell_mode<SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
                                         xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
@@ -128,6 +130,20 @@ __global__ __launch_bounds__(256) void classify_kernel(const float* img, long lo
                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// End of iteration `it` in convergence mode (one thread): if no pass lowered a
+// value the transform is at its fixed point (later passes return at once);
+// otherwise the iteration is counted and the change word cleared.
+__global__ void iteration_end_kernel(unsigned* words, int it) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (ld_relaxed(words + kWordDone) != 0u || ld_relaxed(words + kWordAbort) != 0u) return;
+  if (ld_relaxed(words + kWordChanged) == 0u) {
+    __hip_atomic_store(words + kWordDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  __hip_atomic_store(words + kWordIters, (unsigned)it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(words + kWordChanged, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // out = v * mask, 16 bytes per thread and iteration when both arrays are
 // 16-byte aligned (a plain streaming kernel; also the reference for the
 // achievable HBM rate).
@@ -218,6 +234,11 @@ hipError_t launch_classify(const float* image, long long n, unsigned* words, hip
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, image, n, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_iteration_end(unsigned* words, int it, hipStream_t stream) {
+  hipLaunchKernelGGL(iteration_end_kernel, dim3(1), dim3(64), 0, stream, words, it);
   return hipGetLastError();
 }
 

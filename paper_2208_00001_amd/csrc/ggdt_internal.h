@@ -12,6 +12,11 @@ namespace ggdt {
 constexpr int kHeaderWords = 64;
 constexpr int kWordAbort = 0;   // non-zero once a bounded wait expired (watchdog)
 constexpr int kWordClass = 1;   // image classification bits, see below
+// Convergence mode: set by a pass that lowered some value, cleared per iteration;
+// set once an iteration changed nothing; the number of iterations that did.
+constexpr int kWordChanged = 2;
+constexpr int kWordDone = 3;
+constexpr int kWordIters = 4;
 constexpr unsigned kClassTiny = 1u;  // some image value with 0 < |I| < 2^-40
 constexpr unsigned kClassHuge = 2u;  // some image value with |I| > 2^60 or not finite
 
@@ -73,6 +78,7 @@ struct PassDesc {
   float W0[9];         // sqrtf(A[j]), used when lambda == 0
   unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
   int sqrt_normal;     // min_j A[j] >= 2^-96: the general root may use kModeGeneralN
+  int converge;        // convergence mode: skip when done, report changes in kWordChanged
 };
 
 // Reverse of one forward pass (see backward_device.h).  Geometry fields as in
@@ -155,5 +161,6 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
 hipError_t launch_reset(unsigned* ws, long long nwords, hipStream_t stream);
 hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream);
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream);
+hipError_t launch_iteration_end(unsigned* words, int it, hipStream_t stream);
 
 }  // namespace ggdt

@@ -227,6 +227,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     }
   };
 
+  int chg = 0;  // an own cell of this workgroup was lowered (convergence mode)
   Item cur = item_of(0);
   if (SCANC)
     stage(cur);
@@ -339,6 +340,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         }
         Pc[tid] = make_float2(best, ixj);
         if (e == 0) {
+          chg |= best < dd[i + 1];
           const int x = xof(cur, i + 1);
           // per-step stores spread over the steps' barrier stalls; the
           // scan-contiguous layout stages its results for run-wise writes
@@ -374,6 +376,8 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     }
     cur = nxt;
   }
+  if (g.converge && __syncthreads_or(chg) && tid == 0)
+    __hip_atomic_store(words + kWordChanged, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 

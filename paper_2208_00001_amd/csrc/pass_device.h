@@ -164,6 +164,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
     }
   }
 
+  int chg = 0;  // an own cell of this workgroup was lowered (convergence mode)
   for (int c = 0; c < g.nchunk; ++c) {
     const int t0 = 1 + c * K;
     const int kk = min(K, Na - t0);
@@ -401,6 +402,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
           if (tid + u * NT >= cnt) continue;
           const int lx = lxs[u], pp = pps[u], qq = qqs[u];
           float best = g.init ? g.v * dold[u] : dold[u];
+          const float before = best;
           int choice = 0;
           const float* sx = StI + sidx(i + 1, lx);
           const float* sy = StI + sidx(i, lx);
@@ -424,6 +426,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
           }
           Pc[lx] = make_float2(best, ix0[u]);
           if (pp >= p0 && pp < p0 + TP && qq >= q0 && qq < q0 + TQ) {
+            chg |= best < before;
             const int own = (NDIM == 3 ? (pp - p0) * TQ : 0) + (qq - q0);
             const int x = k * g.sa + pp * g.sp + qq * g.sq;
             if (SCANC)
@@ -458,6 +461,8 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       }
     }
   }
+  if (g.converge && __syncthreads_or(chg) && threadIdx.x == 0)
+    __hip_atomic_store(words + kWordChanged, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
