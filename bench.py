@@ -19,6 +19,7 @@ Also reported (same JSON line):
                 against the MI355X HBM peak (8 TB/s) and against the measured rate
                 of a streaming kernel on 2 GiB; traffic from rocprofv3 counters
                 when a summary for the current kernel source exists
+  converge      the same volume run to its fixed point (iterations and time)
   configs_2d    the 128^2 and 2048^2 x 3 images, voxel-updates/s per lambda
   cpu_baseline  the CPU oracle (single thread) on a bounded sample: one
                 iteration (6 passes) of the same volume
@@ -154,6 +155,27 @@ def bench_small_configs(reps=5):
             vu = int(np.prod(m.shape)) * 4 * c["iterations"]
             res[f"{name}-lam{c['lam']:g}"] = {"ms": ms, "value": vu / (ms * 1e-3), "unit": "voxel-updates/s"}
     return res
+
+
+def bench_converge(c, reps=3):
+    """The 3D volume run to its fixed point (the exact grid shortest-path
+    distance): iterations needed and time."""
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+
+    dev = "cuda:0"
+    img = torch.from_numpy(c["image"]).to(dev)
+    m = torch.from_numpy(c["mask"]).to(dev)
+    out = torch.empty_like(m)
+    ws = B.new_workspace(tuple(m.shape), 1, dev)
+    _, n = B.ggdt_converge(img, m, c["spacing"], c["v"], c["lam"], 200, out=out, workspace=ws)
+    ms = _time(lambda: B.ggdt_converge(img, m, c["spacing"], c["v"], c["lam"], 200, out=out, workspace=ws), reps)
+    vu = int(np.prod(m.shape)) * 6 * (n + 1)
+    return {"workload": c["name"] + " to its fixed point", "iterations_changing": n,
+            "iterations_run": n + 1, "ms": ms, "voxel_updates": vu, "value": vu / (ms * 1e-3),
+            "unit": "voxel-updates/s"}
 
 
 def _time(fn, reps):
@@ -337,6 +359,7 @@ def main():
                      "launches_timed": len(durs), "avg_launch_ms": avg_ms},
     }
     if not args.no_batched:
+        line["converge"] = bench_converge(c)
         line["configs_2d"] = bench_small_configs()
         line["batched"] = bench_batched(max(3, min(args.steps, 10)))
         line["backward"] = bench_backward(max(3, min(args.steps, 10)))
