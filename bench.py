@@ -41,6 +41,8 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel-updates/s + HBM GB/s vs peak, 3D 256³ GGDT; batched & backward vs plain"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VU = 12  # lambda = 1, C = 1: image(x) 4 + D_old(x) 4 + D(x) 4
+# backward, C = 1: record 1 + image(x) 4 + adjoint read 4 / write 4 + image gradient read 4 / write 4
+BWD_BYTES_PER_VU = 21
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pass_kernel_3d_256_pmc.json")
 
 
@@ -224,8 +226,12 @@ def bench_batched(reps):
     ms_p = _time(plain, reps)
     same = all(torch.equal(o, b) for o, b in zip(outs, plan.outputs))
     plan.close()
+    gbs = BYTES_PER_VU * vu / (ms_b * 1e-3) / 1e9
     return {"workload": "64 ragged instances (48 3D + 16 2D), lambda U[0,1], 2-4 iterations",
             "voxel_updates": vu, "batched_ms": ms_b, "plain_ms": ms_p, "speedup": ms_p / ms_b,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_voxel_update": BYTES_PER_VU,
+                         "note": "whole batched launch (graph replay), algorithmic bytes"},
             "batched_value": vu / (ms_b * 1e-3), "plain_value": vu / (ms_p * 1e-3), "unit": "voxel-updates/s",
             "tuning": best["tuning"], "tuning_trials": best["trials"], "outputs_identical": same}
 
@@ -263,10 +269,14 @@ def bench_backward(reps):
     ms_bb = _time(plan.backward, reps)
     assert plan.status() == 0, "watchdog fired (backward)"
     plan.close()
+    gbs = BWD_BYTES_PER_VU * vu / (ms_bb * 1e-3) / 1e9
     return {"workload": "4 x 128^3, lambda 0.7, soft mask, v 10, 3 iterations, L = sum(W * D)",
             "voxel_updates_forward": vu, "batched_fwd_bwd_ms": ms_b, "plain_fwd_bwd_ms": ms_p,
             "speedup": ms_p / ms_b, "batched_forward_ms": ms_bf, "batched_backward_ms": ms_bb,
-            "unit": "ms per forward+backward"}
+            "unit": "ms per forward+backward",
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_voxel_update": BWD_BYTES_PER_VU,
+                         "note": "batched backward launch, algorithmic bytes"}}
 
 
 def main():
