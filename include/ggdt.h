@@ -215,7 +215,11 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
 int ggdt_batched_run(const ggdt_plan* plan, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Run every instance's backward in one persistent launch (all instances need
- * records, grad_out, grad_image and grad_softmask). */
+ * records, grad_out, grad_image and grad_softmask).  GGDT_ERR_UNSUPPORTED when
+ * the plan holds no reverse tables: some instance lacks those buffers, or the
+ * batch's channel count exceeds what one reverse workgroup's LDS holds (2D
+ * images: C <= 2, volumes: C <= 3; the per-instance backward has no such limit
+ * below C = 8). */
 int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 

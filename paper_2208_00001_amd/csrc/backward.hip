@@ -1,5 +1,6 @@
 // Backward (reverse-mode) kernels: one launch per reversed pass of one instance,
 // and the batched persistent launch over many instances (see backward_device.h).
+#include "backward_cell.h"
 #include "backward_device.h"
 
 namespace ggdt {
@@ -13,6 +14,19 @@ __global__ __launch_bounds__(kThreads) void bwd_pass_kernel(BwdDesc g, unsigned*
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   run_bwd_pass_mode<NDIM, TP, TQ, K, SCANC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
                                             xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Single-channel 3D reversed passes on 16 x 16 tiles with K = 8: one thread per box cell.
+__global__ __launch_bounds__(kCellThreads) void bwd_pass_cell_kernel(BwdDesc g, unsigned* words,
+                                                                     unsigned long long limit) {
+  __shared__ float lds[(kBwdCellLdsBytes + 3) / 4];
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  run_bwd_pass_cell_mode(&g, g.xbuf, words, words + kWordClass, limit, lds, xcd_remap(blockIdx.x, gridDim.x),
+                         gridDim.x);
+}
+
+bool use_bwd_cell(const BwdDesc& d, int ndim) {
+  return ndim == 3 && d.C == 1 && d.K == kCellK && d.TP == kCellTP && d.TQ == kCellTQ;
 }
 
 using BwdKernel = void (*)(BwdDesc, unsigned*, unsigned long long);
@@ -45,12 +59,13 @@ size_t bwd_lds(int ndim, int K, int C, bool scanc) {
   return 0;
 }
 
-int capacity_of(const void* fn, size_t lds) {
+int capacity_of(const void* fn, size_t lds, int threads = kThreads) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess) return 0;
+  if (lds > 0 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
   return per_cu * cus;
 }
 
@@ -84,7 +99,13 @@ __device__ bool bwd_instance_barrier(unsigned* counter, unsigned target, unsigne
   return ok;
 }
 
-__global__ __launch_bounds__(kThreads) void batched_bwd_kernel(const BatchInst* __restrict__ insts, int ninst,
+// Batched reverse workgroups have 1024 threads.  Class 0 (every instance a
+// single-channel volume): the thread-per-cell reverse pass only; class 1: the
+// tile reverse passes (2D and 3D) with 1024 threads.
+static_assert(kBwdBatchKCell == kCellK, "batched single-channel 3D reverse passes use the cell chunk length");
+
+template <bool CELL3D>
+__global__ __launch_bounds__(kCellThreads) void batched_bwd_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                                const BwdDesc* __restrict__ passes, unsigned char* ws,
                                                                unsigned long long limit) {
   extern __shared__ float lds[];
@@ -106,13 +127,17 @@ __global__ __launch_bounds__(kThreads) void batched_bwd_kernel(const BatchInst* 
   for (int p = 0; p < in.npass; ++p) {
     const BwdDesc* gp = passes + in.pass0 + p;
     const bool scanc = gp->sa == 1;
+    constexpr int NT = kCellThreads;
     bool ok;
-    if (in.ndim == 3)
-      ok = scanc ? run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, true>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
-                 : run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, false>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
-    else
-      ok = scanc ? run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, true>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
-                 : run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, false>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    if constexpr (CELL3D) {
+      ok = run_bwd_pass_cell_mode(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    } else if (in.ndim == 3) {
+      ok = scanc ? run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, true, NT>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
+                 : run_bwd_pass_mode<3, kTP3, kTQ3, kBwdBatchK3, false, NT>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    } else {
+      ok = scanc ? run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, true, NT>(gp, xbuf, words, cls, limit, lds, wg, in.nwg)
+                 : run_bwd_pass_mode<2, 1, kTQ2, kBwdBatchK2, false, NT>(gp, xbuf, words, cls, limit, lds, wg, in.nwg);
+    }
     if (!ok) return;
     if (p + 1 < in.npass && !bwd_instance_barrier(ctr, (unsigned)(p + 1) * (unsigned)in.nwg, words, limit)) return;
   }
@@ -121,6 +146,7 @@ __global__ __launch_bounds__(kThreads) void batched_bwd_kernel(const BatchInst* 
 }  // namespace
 
 int bwd_chunk_for(int ndim, int C, bool scan_contiguous) {
+  if (ndim == 3 && C == 1) return kCellK;  // thread-per-cell reverse pass
   const int ks3[2] = {4, 2}, ks2[2] = {16, 8};
   for (int i = 0; i < 2; ++i) {
     const int K = ndim == 3 ? ks3[i] : ks2[i];
@@ -131,6 +157,15 @@ int bwd_chunk_for(int ndim, int C, bool scan_contiguous) {
 
 hipError_t launch_bwd_pass(const BwdDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
                            hipStream_t stream) {
+  if (use_bwd_cell(d, ndim)) {
+    static int cap_cell = 0;
+    if (cap_cell <= 0) cap_cell = capacity_of((const void*)bwd_pass_cell_kernel, 0, kCellThreads);
+    if (cap_cell <= 0) return hipErrorInvalidConfiguration;
+    const int ntiles = d.ntp * d.ntq;
+    const int grid = ntiles < cap_cell ? ntiles : cap_cell;
+    hipLaunchKernelGGL(bwd_pass_cell_kernel, dim3(grid), dim3(kCellThreads), 0, stream, d, words, spin_limit);
+    return hipGetLastError();
+  }
   BwdKernel fn = select_bwd(d, ndim);
   if (!fn) return hipErrorInvalidConfiguration;
   const size_t lds = bwd_lds(ndim, d.K, d.C, d.sa == 1);
@@ -143,25 +178,37 @@ hipError_t launch_bwd_pass(const BwdDesc& d, int ndim, unsigned* words, unsigned
   return hipGetLastError();
 }
 
-size_t batched_bwd_lds_bytes(int C, bool has2d, bool has3d) {
+// c2 / c3: the largest channel count of the batch's 2D / 3D instances (0: none).
+size_t batched_bwd_lds_bytes(int c2, int c3) {
   size_t b = 0;
-  if (has3d) {
-    b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, true>::bytes(C));
-    b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, false>::bytes(C));
+  if (c3 > 0) {
+    if (c3 == 1 && c2 == 0) {
+      b = max(b, kBwdCellLdsBytes);  // class 0: thread-per-cell reverse pass
+    } else {
+      b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, true>::bytes(c3));
+      b = max(b, BLayout<3, kTP3, kTQ3, kBwdBatchK3, false>::bytes(c3));
+    }
   }
-  if (has2d) {
-    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, true>::bytes(C));
-    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, false>::bytes(C));
+  if (c2 > 0) {
+    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, true>::bytes(c2));
+    b = max(b, BLayout<2, 1, kTQ2, kBwdBatchK2, false>::bytes(c2));
   }
   return b;
 }
 
-int batched_bwd_capacity(size_t lds) { return capacity_of((const void*)batched_bwd_kernel, lds); }
+int batched_bwd_capacity(int bclass, size_t lds) {
+  return capacity_of(bclass == 0 ? (const void*)batched_bwd_kernel<true> : (const void*)batched_bwd_kernel<false>,
+                     lds, kCellThreads);
+}
 
-hipError_t launch_batched_bwd(const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws, int grid,
-                              size_t lds, unsigned long long spin_limit, hipStream_t stream) {
-  hipLaunchKernelGGL(batched_bwd_kernel, dim3(grid), dim3(kThreads), lds, stream, insts, ninst, passes, ws,
-                     spin_limit);
+hipError_t launch_batched_bwd(int bclass, const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws,
+                              int grid, size_t lds, unsigned long long spin_limit, hipStream_t stream) {
+  if (bclass == 0)
+    hipLaunchKernelGGL(batched_bwd_kernel<true>, dim3(grid), dim3(kCellThreads), lds, stream, insts, ninst, passes,
+                       ws, spin_limit);
+  else
+    hipLaunchKernelGGL(batched_bwd_kernel<false>, dim3(grid), dim3(kCellThreads), lds, stream, insts, ninst, passes,
+                       ws, spin_limit);
   return hipGetLastError();
 }
 

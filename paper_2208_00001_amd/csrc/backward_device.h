@@ -66,7 +66,7 @@ __device__ __forceinline__ float bwd_edge(const BwdDesc& g, int j, const float* 
   return general_root<MODE>(fmaf(g.lam, s, spatial_term(g, j)));
 }
 
-template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE>
+template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE, int NT = kThreads>
 __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long long* xbuf, unsigned* words,
                                              unsigned long long limit, float* lds, int wg, int G) {
   using L = BLayout<NDIM, TP, TQ, K, SCANC>;
@@ -95,7 +95,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
       const int tp = tile / g.ntq, tq = tile - tp * g.ntq;
       const int p0 = tp * TP, q0 = tq * TQ;
       const int rp = min(TP, Np - p0), rq = min(TQ, Nq - q0);
-      for (int f = tid; f < rp * rq; f += kThreads) {
+      for (int f = tid; f < rp * rq; f += NT) {
         const int r = f / rq, cq = f - r * rq;
         const int pp = p0 + r, qq = q0 + cq;
         const int x = kl * g.sa + pp * g.sp + qq * g.sq;
@@ -161,7 +161,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
 
       // 1. abar_in (m = 1..kk, and m = 0 in chunk 0) and the image (m = 0..mtop)
       // into LDS; expansion of plane m is kk - m (image: at least 1).
-      for (int f0 = 0; f0 < STAGE; f0 += kThreads) {
+      for (int f0 = 0; f0 < STAGE; f0 += NT) {
         const int f = f0 + tid;
         int m, lx, k;
         if (SCANC) {
@@ -191,13 +191,13 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
       // records (m = 0..kk) through registers, in batches of RB byte loads
       // issued together before their LDS stores (the batch bounds the registers
       // held); out-of-plane and unneeded cells read as 0 ("kept").
-      constexpr int NR = (STAGE + kThreads - 1) / kThreads;
+      constexpr int NR = (STAGE + NT - 1) / NT;
       constexpr int RB = NR < 8 ? NR : 8;
       for (int n0 = 0; n0 < NR; n0 += RB) {
         unsigned rv[RB];
 #pragma unroll
         for (int n1 = 0; n1 < RB; ++n1) {
-          const int f = (n0 + n1) * kThreads + tid;
+          const int f = (n0 + n1) * NT + tid;
           int m, lx, k;
           if (SCANC) {
             lx = f / SC;
@@ -218,13 +218,13 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
         }
 #pragma unroll
         for (int n1 = 0; n1 < RB; ++n1) {
-          const int f = (n0 + n1) * kThreads + tid;
+          const int f = (n0 + n1) * NT + tid;
           if (f < STAGE) StR[f] = (unsigned char)rv[n1];
         }
       }
       // own Ibar of the parent planes m = 1..kk
       if (USE_I) {
-        for (int f0 = 0; f0 < K * OWN; f0 += kThreads) {
+        for (int f0 = 0; f0 < K * OWN; f0 += NT) {
           const int f = f0 + tid;
           const int mm = f / OWN, own = f - mm * OWN;
           const int r = (NDIM == 3) ? own / TQ : 0, cq = own - r * TQ;
@@ -239,7 +239,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
       }
 
       // 2. the state on child plane m = 0: exchange words of chunk c - 1.
-      constexpr int MAXB = (NB + kThreads - 1) / kThreads;
+      constexpr int MAXB = (NB + NT - 1) / NT;
       unsigned long long wv[MAXB];
       int lxs[MAXB];
 #pragma unroll
@@ -248,7 +248,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
         const unsigned long long* xin = xbuf + (size_t)((c - 1) & 1) * ntiles * (TP * TQ);
 #pragma unroll
         for (int n = 0; n < MAXB; ++n) {
-          const int lx = tid + n * kThreads;
+          const int lx = tid + n * NT;
           const int br = lx / BQ, bc = lx - br * BQ;
           const int pp = bp0 + br, qq = bq0 + bc;
           bool ok = lx < NB && qq >= 0 && qq < Nq && (NDIM == 2 || (pp >= 0 && pp < Np));
@@ -291,7 +291,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
       __syncthreads();
 #pragma unroll
       for (int n = 0; n < MAXB; ++n) {
-        const int lx = tid + n * kThreads;
+        const int lx = tid + n * NT;
         if (lx >= NB) break;
         float s = 0.0f;
         if (c > 0) {
@@ -315,7 +315,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
         const int lq = max(0, q0 - h), hq = min(Nq, q0 + TQ + h);
         const int rq = hq - lq, cnt = (hp - lp) * rq;
         const float inv_rq = 1.0f / (float)rq;
-        for (int f = tid; f < cnt; f += kThreads) {
+        for (int f = tid; f < cnt; f += NT) {
           int r, cq;
           if (NDIM == 3) {
             r = (int)(((float)f + 0.5f) * inv_rq);
@@ -396,17 +396,17 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
   return true;
 }
 
-template <int NDIM, int TP, int TQ, int K, bool SCANC>
+template <int NDIM, int TP, int TQ, int K, bool SCANC, int NT = kThreads>
 __device__ __forceinline__ bool run_bwd_pass_mode(const BwdDesc* gp, unsigned long long* xbuf, unsigned* words,
                                                   const unsigned* cls_word, unsigned long long limit, float* lds,
                                                   int wg, int G) {
   const int mode = gp->mode;
-  if (mode == kModeLam0) return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam0>(gp, xbuf, words, limit, lds, wg, G);
+  if (mode == kModeLam0) return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam0, NT>(gp, xbuf, words, limit, lds, wg, G);
   if (mode == kModeLam1C1 && ld_relaxed(cls_word) == 0u)
-    return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam1C1>(gp, xbuf, words, limit, lds, wg, G);
+    return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam1C1, NT>(gp, xbuf, words, limit, lds, wg, G);
   if (mode == kModeGeneral && general_n_ok(gp->sqrt_normal, cls_word))
-    return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN>(gp, xbuf, words, limit, lds, wg, G);
-  return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral>(gp, xbuf, words, limit, lds, wg, G);
+    return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN, NT>(gp, xbuf, words, limit, lds, wg, G);
+  return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, NT>(gp, xbuf, words, limit, lds, wg, G);
 }
 
 }  // namespace dev

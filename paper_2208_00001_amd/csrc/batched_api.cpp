@@ -26,6 +26,7 @@ struct ggdt_plan {
   std::vector<long long> npix;
   // backward tables (when every instance has records and gradient buffers)
   bool has_bwd = false;
+  int bclass = 0;
   int bgrid = 0;
   size_t blds = 0;
   size_t fwd_ws = 0;
@@ -92,7 +93,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   if (n < 1) return GGDT_ERR_BAD_SHAPE;
   *plan_out = nullptr;
   std::vector<Problem> prs(n);
-  int maxC = 1;
+  int maxC = 1, maxC2 = 0, maxC3 = 0;
   bool has2d = false, has3d = false, rec = false, any_cls = false;
   for (int i = 0; i < n; ++i) {
     const int rc = validate_instance(instances[i], &prs[i]);
@@ -100,6 +101,8 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     maxC = instances[i].C > maxC ? instances[i].C : maxC;
     has2d |= instances[i].ndim == 2;
     has3d |= instances[i].ndim == 3;
+    if (instances[i].ndim == 2) maxC2 = instances[i].C > maxC2 ? instances[i].C : maxC2;
+    else maxC3 = instances[i].C > maxC3 ? instances[i].C : maxC3;
     rec |= instances[i].records != nullptr;
     any_cls = true;  // the classification decides every instance's edge-cost mode
   }
@@ -206,8 +209,9 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
                instances[i].grad_softmask;
   size_t boff = off;
   if (want_bwd) {
-    const size_t blds = batched_bwd_lds_bytes(maxC, has2d, has3d);
-    int bcap = blds <= kMaxLdsBytes ? batched_bwd_capacity(blds) : 0;
+    const int bclass = (maxC <= 1 && !has2d) ? 0 : 1;
+    const size_t blds = batched_bwd_lds_bytes(maxC2, maxC3);
+    int bcap = blds <= kMaxLdsBytes ? batched_bwd_capacity(bclass, blds) : 0;
     if (tuning && tuning->wg_per_cu > 0 && bcap > 0) {
       int dev = 0, cus = 0;
       if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
@@ -225,7 +229,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
       for (int i = 0; i < n; ++i) {
         const ggdt_instance& in = instances[i];
         const int P = in.iterations * 2 * in.ndim;
-        const int K = in.ndim == 3 ? kBwdBatchK3 : kBwdBatchK2;
+        const int K = in.ndim == 3 ? (bclass == 0 ? kBwdBatchKCell : kBwdBatchK3) : kBwdBatchK2;
         unsigned base = 0;
         for (int q = 0; q < P; ++q) {
           const int p = P - 1 - q;
@@ -290,6 +294,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
         return GGDT_ERR_HIP;
       }
       plan->has_bwd = true;
+      plan->bclass = bclass;
       plan->bgrid = bwg0;
       plan->blds = blds;
     }
@@ -348,8 +353,8 @@ int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspa
       return GGDT_ERR_HIP;
   }
   prof_before(stream);
-  const hipError_t e = launch_batched_bwd(plan->d_binsts, plan->n, plan->d_bpasses, ws, plan->bgrid, plan->blds,
-                                          g_spin_limit, stream);
+  const hipError_t e = launch_batched_bwd(plan->bclass, plan->d_binsts, plan->n, plan->d_bpasses, ws, plan->bgrid,
+                                          plan->blds, g_spin_limit, stream);
   prof_after(stream);
   if (e != hipSuccess) return GGDT_ERR_HIP;
   for (int i = 0; i < plan->n; ++i) {

@@ -142,12 +142,17 @@ hipError_t launch_batched_classify(const BatchInst* insts, int ninst, unsigned c
 int bwd_chunk_for(int ndim, int C, bool scan_contiguous);
 hipError_t launch_bwd_pass(const BwdDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
                            hipStream_t stream);
-size_t batched_bwd_lds_bytes(int C, bool has2d, bool has3d);
-int batched_bwd_capacity(size_t lds);
-hipError_t launch_batched_bwd(const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws, int grid,
-                              size_t lds, unsigned long long spin_limit, hipStream_t stream);
+size_t batched_bwd_lds_bytes(int c2, int c3);
+// Batched reverse kernel class: 0 when every instance is a single-channel volume
+// (thread-per-cell reverse pass), else 1 (tile reverse passes).
+int batched_bwd_capacity(int bclass, size_t lds);
+hipError_t launch_batched_bwd(int bclass, const BatchInst* insts, int ninst, const BwdDesc* passes, unsigned char* ws,
+                              int grid, size_t lds, unsigned long long spin_limit, hipStream_t stream);
 // Chunk lengths of the batched backward kernel.
 constexpr int kBwdBatchK3 = 4, kBwdBatchK2 = 16;
+// Chunk length of single-channel 3D instances in batched reverse passes (the
+// thread-per-cell reverse pass).
+constexpr int kBwdBatchKCell = 8;
 
 // Pick the chunk length for a tile geometry so that the kernel's LDS fits.
 // Returns 0 if no instantiation fits (too many channels).

@@ -100,3 +100,46 @@ def test_config4_batch_equals_plain_launches_and_oracle():
         if ref and ref["image_sha256"] == _sha(c["image"]) and ref["mask_sha256"] == _sha(c["mask"]):
             assert _sha(got) == ref["out_sha256"], f"instance {i} {c['name']}: differs from the oracle digest"
     plan.close()
+
+
+@pytest.mark.parametrize("kind", ["mixed", "volumes"])
+def test_small_ragged_batch_backward(kind):
+    """Batched forward with records + batched backward for every instance, vs the
+    single-instance launches and the oracle's FP32 reverse pass (bitwise).
+    'mixed': 2D and 3D, 1-3 channels (tile reverse passes); 'volumes':
+    single-channel volumes of different shapes only (thread-per-cell reverse
+    pass, with more workgroups than some passes have tiles)."""
+    from paper_2208_00001_amd import binding as B
+    from paper_2208_00001_amd.batched import BatchedPlan
+    if kind == "mixed":
+        specs = [((29, 23, 31), 1, 0.7, 2), ((200, 137), 2, 0.5, 2), ((17, 40, 22), 3, 0.4, 1), ((90, 301), 1, 1.0, 2),
+                 ((12, 13, 70), 1, 0.0, 2)]  # channel counts within the batched reverse pass's LDS (2D <= 2, 3D <= 3)
+    else:
+        specs = [((40, 33, 71), 1, 0.7, 2), ((19, 64, 17), 1, 1.0, 2), ((70, 18, 23), 1, 0.3, 1),
+                 ((33, 33, 33), 1, 0.0, 2)]
+    cases = []
+    for k, (shape, C, lam, it) in enumerate(specs):
+        c = synth.small_case(shape, C=C, seed=400 + k, lam=lam, iterations=it, soft=True, v=8.0)
+        c["weight"] = np.random.default_rng(400 + k).standard_normal(c["mask"].shape).astype(np.float32)
+        cases.append(c)
+    inst = to_instances(cases, True)
+    for d, c in zip(inst, cases):
+        d["grad_out"] = to_dev(c["weight"])
+    plan = BatchedPlan(inst)
+    print("plan", plan.info(), flush=True)
+    plan.run()
+    grads = plan.backward()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    for k, (c, d) in enumerate(zip(cases, plan.inst)):
+        print(f"instance {c['name']} lam={c['lam']} it={c['iterations']}", flush=True)
+        gi, gm = B.ggdt_backward(d["image"], d["records"], d["grad_out"], c["spacing"], c["v"], c["lam"],
+                                 c["iterations"])
+        assert torch.equal(gi, grads[k][0]) and torch.equal(gm, grads[k][1]), c["name"]
+        _, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], c["iterations"], "f32",
+                                 records=True)
+        rgi, rgm = oracle.backward(c["image"], ref_rec, c["weight"], c["spacing"], c["v"], c["lam"], c["iterations"],
+                                   "f32")
+        assert assert_parity(to_host(grads[k][1]), rgm, what="dL/dM"), c["name"]
+        assert assert_parity(to_host(grads[k][0]).reshape(rgi.shape), rgi, what="dL/dI"), c["name"]
+    plan.close()
