@@ -10,7 +10,7 @@ using namespace dev;
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC>
 __global__ __launch_bounds__(kThreads) void bwd_pass_kernel(BwdDesc g, unsigned* words, unsigned long long limit) {
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) float lds[];
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   run_bwd_pass_mode<NDIM, TP, TQ, K, SCANC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
                                             xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
@@ -108,7 +108,10 @@ template <bool CELL3D>
 __global__ __launch_bounds__(kCellThreads) void batched_bwd_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                                const BwdDesc* __restrict__ passes, unsigned char* ws,
                                                                unsigned long long limit) {
-  extern __shared__ float lds[];
+  // The dynamic area is placed after the static LDS variables (the pass
+  // barrier's flag): without the alignment it would start 4 bytes in, and every
+  // 8- or 16-byte LDS access of the pass would be misaligned.
+  extern __shared__ __align__(16) float lds[];
   unsigned* words = reinterpret_cast<unsigned*>(ws);
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   const int b = xcd_remap(blockIdx.x, gridDim.x);

@@ -28,9 +28,10 @@
 namespace ggdt {
 namespace dev {
 
-// LDS of the reverse pass: two planes of (abar, I, coefficient, record bits)
-// and two image planes (a step's grandparent plane), one fail word.
-constexpr size_t kBwdCellLdsBytes = sizeof(float4) * 2 * kCellThreads + sizeof(float) * 2 * kCellThreads +
+// LDS of the reverse pass: two planes of (abar, record bits), two of (I,
+// coefficient) (read by own cells only), two image planes (a step's grandparent
+// plane), one fail word.
+constexpr size_t kBwdCellLdsBytes = sizeof(float2) * 4 * kCellThreads + sizeof(float) * 2 * kCellThreads +
                                     sizeof(int);
 // record bits of a published cell: the record (0 or 1 + j), and kCoefValid
 // when its parent edge has w > 0 (its coefficient then enters the parent's Ibar)
@@ -58,6 +59,12 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
   BwdDesc g = *gp;
   if (g.a_in_off >= 0) g.a_in = reinterpret_cast<const float*>(reinterpret_cast<unsigned char*>(words) + g.a_in_off);
   if (g.a_out_off >= 0) g.a_out = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(words) + g.a_out_off);
+  // global-memory views of the descriptor's arrays
+  const gmem<const float> gImage = to_gmem(g.image);
+  const gmem<const uint8_t> gRec = to_gmem(g.rec);
+  const gmem<const float> gAin = to_gmem(g.a_in);
+  const gmem<float> gAout = to_gmem(g.a_out);
+  const gmem<float> gGI = to_gmem(g.gI);
   const int tid = threadIdx.x;
   const int br = tid / BQ, bc = tid - br * BQ;
   const int e = max(max(max(K - br, br - (K + TP - 1)), max(K - bc, bc - (K + TQ - 1))), 0);
@@ -66,9 +73,11 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
   if (wg >= ntiles) return true;  // a batched instance may hold more workgroups than tiles
   const int Na = g.Na, Np = g.Np, Nq = g.Nq;
   constexpr bool USE_I = MODE != kModeLam0;
-  float4* const S0 = reinterpret_cast<float4*>(lds);
-  float4* const S1 = S0 + NB;
-  float* const J0 = reinterpret_cast<float*>(S1 + NB);
+  float2* const S0 = reinterpret_cast<float2*>(lds);  // (abar, record bits)
+  float2* const S1 = S0 + NB;
+  float2* const V0 = S1 + NB;  // (I, coefficient)
+  float2* const V1 = V0 + NB;
+  float* const J0 = reinterpret_cast<float*>(V1 + NB);
   float* const J1 = J0 + NB;
   int* const failw = reinterpret_cast<int*>(J1 + NB);
   if (tid == 0) *failw = 0;  // read only after a barrier
@@ -82,8 +91,8 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
       const int pp = tp * TP - K + br, qq = tq * TQ - K + bc;
       if (e != 0 || pp >= Np || qq >= Nq) continue;
       const int x = kl * g.sa + pp * g.sp + qq * g.sq;
-      const float a = g.a_in[x];
-      const int rc = g.rec[x];
+      const float a = gAin[x];
+      const int rc = gRec[x];
       const int j = rc - 1;
       const int dp = j / 3 - 1, dq = j % 3 - 1;
       // a parent outside the grid only comes from records of another schedule: skip it
@@ -91,14 +100,14 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
                           qq + dq < Nq;
       if (USE_I && par_ok) {
         const int y = kpar * g.sa + (pp + dp) * g.sp + (qq + dq) * g.sq;
-        const float ix = g.image[x], iy = g.image[y];
+        const float ix = gImage[x], iy = gImage[y];
         const float w = bwd_cell_edge_rt<MODE>(g, j, ix, iy);
         if (w > 0.0f) {
           const float coef = (a * g.lam) / w;
-          g.gI[x] = g.gI[x] + coef * (ix - iy);
+          gGI[x] = gGI[x] + coef * (ix - iy);
         }
       }
-      g.a_out[x] = rc != 0 ? 0.0f : a;
+      gAout[x] = rc != 0 ? 0.0f : a;
     }
   }
 
@@ -134,27 +143,27 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
   // Plane m as a child (step m) and as a parent (step m - 1) is used by the
   // cells within distance kk - m; the parent edges of the cells within distance
   // 1 read images one plane further, at distance 2.
-  // Records of planes 0..K are kept four to a register.
+  // Records of planes 0..K: fetched one byte per register, kept four to a
+  // register for the item being walked.
   constexpr int NRW = (K + 1 + 3) / 4;
   float nA[K + 2], nI[K + 2];
-  unsigned nR[NRW];
+  int nR[K + 1];  // record bytes, unpacked here so that their loads need no early wait
   // (inlined: called twice, and a call would put the captured arrays in memory)
   auto fetch = [&](const Item& it) __attribute__((always_inline)) {
-#pragma unroll
-    for (int w = 0; w < NRW; ++w) nR[w] = 0u;
 #pragma unroll
     for (int m = 0; m <= K + 1; ++m) {
       const bool in_m = it.in && m <= it.mtop;
       const bool need = in_m && e <= it.kk - m;
       nA[m] = 0.0f;
       nI[m] = 0.0f;
+      if (m <= K) nR[m] = 0;
       if (in_m) {
         const int x = xof(it, m);
         if (m <= K && need && m <= it.kk) {
-          if (m >= 1 || it.c == 0) nA[m] = g.a_in[x];
-          nR[m >> 2] |= (unsigned)g.rec[x] << (8 * (m & 3));
+          if (m >= 1 || it.c == 0) nA[m] = gAin[x];
+          nR[m] = gRec[x];
         }
-        if (USE_I && (need || e <= 2)) nI[m] = g.image[x];
+        if (USE_I && (need || e <= 2)) nI[m] = gImage[x];
       }
     }
   };
@@ -178,10 +187,12 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
       // rest, so that it costs no registers during the previous item's steps;
       // the exchange wait below covers its latency
       gi[m] = 0.0f;
-      if (USE_I && e == 0 && cur.in && m >= 1 && m <= kk) gi[m] = g.gI[xof(cur, m)];
+      if (USE_I && e == 0 && cur.in && m >= 1 && m <= kk) gi[m] = gGI[xof(cur, m)];
     }
 #pragma unroll
-    for (int w = 0; w < NRW; ++w) rec[w] = nR[w];
+    for (int w = 0; w < NRW; ++w) rec[w] = 0u;
+#pragma unroll
+    for (int m = 0; m <= K; ++m) rec[m >> 2] |= (unsigned)nR[m] << (8 * (m & 3));
 
     // Plane 0 of the chunk: abar_in of the pass's last plane in chunk 0, else
     // the state the previous chunk published (this tile's and its neighbours').
@@ -237,16 +248,19 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
           valid = kCoefValid;
         }
       }
-      S0[tid] = make_float4(s0, ix[0], cf, __int_as_float(r0 | valid));
+      S0[tid] = make_float2(s0, __int_as_float(r0 | valid));
+      V0[tid] = make_float2(ix[0], cf);
       J0[tid] = ix[2];
-      if (!cur.in) S1[tid] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(0));
+      if (!cur.in) S1[tid] = make_float2(0.0f, __int_as_float(0));
     }
     step_barrier();
     if (has_next) fetch(nxt);
 
     // Parent planes m = i + 1 for i = 0 .. kk - 1.
-    float4* Sc = S0;
-    float4* Sn = S1;
+    float2* Sc = S0;
+    float2* Sn = S1;
+    float2* Vc = V0;
+    float2* Vn = V1;
     float* Jc = J0;
     float* Jn = J1;
     unsigned long long* xout = xbuf + (size_t)(c & 1) * ntiles * (TP * TQ) + (size_t)cur.tile * (TP * TQ);
@@ -257,12 +271,12 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
         const float iy = ix[i + 1];
         const int ry = rec_of(rec, i + 1);
         float a = ain[i + 1];
-        float4 ch[9];  // children x_j = y - delta_j: (abar, I, coefficient, record bits)
+        float2 ch[9];  // children x_j = y - delta_j: (abar, record bits)
 #pragma unroll
         for (int j = 0; j < 9; ++j) ch[j] = Sc[tid - (j / 3 - 1) * BQ - (j % 3 - 1)];
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-          if ((__float_as_int(ch[j].w) & 0xff) == 1 + j) a = a + ch[j].x;
+          if ((__float_as_int(ch[j].y) & 0xff) == 1 + j) a = a + ch[j].x;
         // this cell's parent edge (cells within distance 1 of the tile)
         float cf = 0.0f, iyp = 0.0f;
         int valid = 0;
@@ -279,22 +293,31 @@ __device__ __forceinline__ bool run_bwd_pass_cell(const BwdDesc* gp, unsigned lo
           const int x = xof(cur, i + 1);
           if (USE_I) {
             float gy = gi[i + 1];
+            float2 v[9];  // (I(x_j), coef(x_j)), read together; applied where the record matches
 #pragma unroll
-            for (int j = 0; j < 9; ++j)
-              if ((__float_as_int(ch[j].w) & 0x1ff) == (kCoefValid | (1 + j))) gy = gy - ch[j].z * (ch[j].y - iy);
+            for (int j = 0; j < 9; ++j) v[j] = Vc[tid - (j / 3 - 1) * BQ - (j % 3 - 1)];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+              const float t = gy - v[j].y * (v[j].x - iy);
+              gy = (__float_as_int(ch[j].y) & 0x1ff) == (kCoefValid | (1 + j)) ? t : gy;
+            }
             if (valid) gy = gy + cf * (iy - iyp);
-            g.gI[x] = gy;
+            gGI[x] = gy;
           }
-          g.a_out[x] = ry != 0 ? 0.0f : a;
+          gAout[x] = ry != 0 ? 0.0f : a;
           if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(a));
         }
-        Sn[tid] = make_float4(a, iy, cf, __int_as_float(ry | valid));
+        Sn[tid] = make_float2(a, __int_as_float(ry | valid));
+        Vn[tid] = make_float2(iy, cf);
         if (i + 3 <= K + 1) Jn[tid] = ix[i + 3 <= K + 1 ? i + 3 : K + 1];  // grandparent plane of step i + 1
       }
       step_barrier();
-      float4* ts = Sc;
+      float2* ts = Sc;
       Sc = Sn;
       Sn = ts;
+      float2* tv = Vc;
+      Vc = Vn;
+      Vn = tv;
       float* tj = Jc;
       Jc = Jn;
       Jn = tj;

@@ -74,6 +74,12 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
   BwdDesc g = *gp;
   if (g.a_in_off >= 0) g.a_in = reinterpret_cast<const float*>(reinterpret_cast<unsigned char*>(words) + g.a_in_off);
   if (g.a_out_off >= 0) g.a_out = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(words) + g.a_out_off);
+  // global-memory views of the descriptor's arrays
+  const gmem<const float> gImage = to_gmem(g.image);
+  const gmem<const uint8_t> gRec = to_gmem(g.rec);
+  const gmem<const float> gAin = to_gmem(g.a_in);
+  const gmem<float> gAout = to_gmem(g.a_out);
+  const gmem<float> gGI = to_gmem(g.gI);
   const int tid = threadIdx.x;
   const int wave0 = tid & ~63;
   float* const Sbuf0 = lds;
@@ -99,8 +105,8 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
         const int r = f / rq, cq = f - r * rq;
         const int pp = p0 + r, qq = q0 + cq;
         const int x = kl * g.sa + pp * g.sp + qq * g.sq;
-        const float a = g.a_in[x];
-        const int rc = g.rec[x];
+        const float a = gAin[x];
+        const int rc = gRec[x];
         const int j = rc - 1;
         const int dp = NDIM == 3 ? j / 3 - 1 : 0, dq = (NDIM == 3 ? j % 3 : j) - 1;
         // a parent outside the grid only comes from records of another schedule: skip it
@@ -108,14 +114,14 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
                             qq + dq >= 0 && qq + dq < Nq;
         if (USE_I && par_ok) {
           const int y = kpar * g.sa + (pp + dp) * g.sp + (qq + dq) * g.sq;
-          const float d0 = g.image[x] - g.image[y];
+          const float d0 = gImage[x] - gImage[y];
           float w;
           if (MODE == kModeLam1C1) {
             w = fabsf(d0);
           } else {
             float s = d0 * d0;
             for (int c = 1; c < g.C; ++c) {
-              const float dc = g.image[(long long)c * g.N + x] - g.image[(long long)c * g.N + y];
+              const float dc = gImage[(long long)c * g.N + x] - gImage[(long long)c * g.N + y];
               s = fmaf(dc, dc, s);
             }
             w = general_root<MODE>(fmaf(g.lam, s, spatial_term(g, j)));
@@ -123,12 +129,12 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
           if (w > 0.0f) {
             const float coef = (a * g.lam) / w;
             for (int c = 0; c < g.C; ++c) {
-              const float dc = g.image[(long long)c * g.N + x] - g.image[(long long)c * g.N + y];
-              g.gI[(long long)c * g.N + x] = g.gI[(long long)c * g.N + x] + coef * dc;
+              const float dc = gImage[(long long)c * g.N + x] - gImage[(long long)c * g.N + y];
+              gGI[(long long)c * g.N + x] = gGI[(long long)c * g.N + x] + coef * dc;
             }
           }
         }
-        g.a_out[x] = rc != 0 ? 0.0f : a;
+        gAout[x] = rc != 0 ? 0.0f : a;
       }
     }
   }
@@ -182,10 +188,10 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
         const int e = in ? outside<NDIM, TP, TQ>(pp, qq, p0, q0) : 0;
         const int x = in ? k * g.sa + pp * g.sp + qq * g.sq : 0;
         if (in && m <= kk && (m >= 1 || c == 0) && e <= kk - m)
-          __builtin_amdgcn_global_load_lds(g.a_in + x, StA + f0 + wave0, 4, 0, 0);
+          __builtin_amdgcn_global_load_lds(gAin + x, StA + f0 + wave0, 4, 0, 0);
         if (in && e <= max(kk - m, 1))
           for (int ch = 0; ch < nch; ++ch)
-            __builtin_amdgcn_global_load_lds(g.image + (long long)ch * g.N + x, StI + ch * STAGE + f0 + wave0, 4, 0,
+            __builtin_amdgcn_global_load_lds(gImage + (long long)ch * g.N + x, StI + ch * STAGE + f0 + wave0, 4, 0,
                                              0);
       }
       // records (m = 0..kk) through registers, in batches of RB byte loads
@@ -214,7 +220,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
           const int pp = bp0 + br, qq = bq0 + bc;
           const bool in = f < STAGE && m >= 0 && m <= kk && k >= 0 && k < Na && qq >= 0 && qq < Nq &&
                           (NDIM == 2 || (pp >= 0 && pp < Np)) && outside<NDIM, TP, TQ>(pp, qq, p0, q0) <= kk - m;
-          rv[n1] = in ? (unsigned)g.rec[k * g.sa + pp * g.sp + qq * g.sq] : 0u;
+          rv[n1] = in ? (unsigned)gRec[k * g.sa + pp * g.sp + qq * g.sq] : 0u;
         }
 #pragma unroll
         for (int n1 = 0; n1 < RB; ++n1) {
@@ -232,7 +238,7 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
           if (mm < kk && pp < Np && qq < Nq) {
             const int x = kof(mm + 1) * g.sa + pp * g.sp + qq * g.sq;
             for (int ch = 0; ch < g.C; ++ch)
-              __builtin_amdgcn_global_load_lds(g.gI + (long long)ch * g.N + x, StG + ch * K * OWN + f0 + wave0, 4, 0,
+              __builtin_amdgcn_global_load_lds(gGI + (long long)ch * g.N + x, StG + ch * K * OWN + f0 + wave0, 4, 0,
                                                0);
           }
         }
@@ -379,9 +385,9 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
                   }
                 }
               }
-              for (int ch = 0; ch < g.C; ++ch) g.gI[(long long)ch * g.N + y] = gy[ch * K * OWN];
+              for (int ch = 0; ch < g.C; ++ch) gGI[(long long)ch * g.N + y] = gy[ch * K * OWN];
             }
-            g.a_out[y] = ry != 0 ? 0.0f : a;
+            gAout[y] = ry != 0 ? 0.0f : a;
             if (i == kk - 1)
               st64_relaxed(xout + own, ((unsigned long long)epoch_out << 32) | __float_as_uint(a));
           }

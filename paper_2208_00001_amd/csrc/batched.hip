@@ -69,7 +69,7 @@ template <int K3, int K2, bool REC>
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                            const PassDesc* __restrict__ passes, unsigned char* ws,
                                                            unsigned long long limit) {
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) float lds[];
   unsigned* words = reinterpret_cast<unsigned*>(ws);
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void batched_classify_kernel(const BatchInst* 
     unsigned bits = 0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < in.nimg; t += stride) {
-      const float a = fabsf(in.image[t]);
+      const float a = fabsf(to_gmem(in.image)[t]);
       if (!(a <= 0x1p60f)) bits |= kClassHuge;
       else if (a != 0.0f && a < 0x1p-40f) bits |= kClassTiny;
     }

@@ -11,7 +11,7 @@ using namespace dev;
 
 template <int NDIM, int TP, int TQ, int K, bool SCANC, int RMODE, bool REC>
 __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* words, unsigned long long limit) {
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) float lds[];
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
   run_pass_mode<NDIM, TP, TQ, K, SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,

@@ -87,6 +87,11 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   constexpr int TP = kCellTP, TQ = kCellTQ, K = kCellK, BQ = kCellBQ, NB = kCellThreads;
   constexpr int SC = kCellSC, SCR = kCellSCR, STAGE = kCellStage;
   const PassDesc g = *gp;
+  // global-memory views of the descriptor's arrays
+  const gmem<const float> gImage = to_gmem(g.image);
+  const gmem<const float> gMask = to_gmem(g.mask);
+  const gmem<float> gD = to_gmem(g.D);
+  const gmem<uint8_t> gRec = to_gmem(g.rec);
   const int tid = threadIdx.x;
   const int br = tid / BQ, bc = tid - br * BQ;
   // Chebyshev distance of the box cell outside the tile (0 for the tile's own cells)
@@ -115,14 +120,14 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
       const int pp = tp * TP - K + br, qq = tq * TQ - K + bc;
       if (e == 0 && pp < Np && qq < Nq) {
         const int x = kf * g.sa + pp * g.sp + qq * g.sq;
-        if (g.init) g.D[x] = g.v * g.mask[x];
-        if (REC && g.rec) g.rec[x] = 0;
+        if (g.init) gD[x] = g.v * gMask[x];
+        if (REC && g.rec) gRec[x] = 0;
       }
     }
   }
 
   if (tid == 0) *lds.fail = 0;  // read only after a barrier
-  const float* const dsrc0 = g.init ? g.mask : g.D;
+  const gmem<const float> dsrc0 = g.init ? gMask : (gmem<const float>)gD;
   const float vscale = g.init ? g.v : 1.0f;
   // Work items in order: chunk-major, then this workgroup's tiles.  The next
   // item's image and D_old are fetched while the current item's planes are
@@ -173,7 +178,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
       nd[j] = 0.0f;
       if (need) {
         const int x = xof(it, j);
-        if (USE_I) nx[j] = g.image[x];
+        if (USE_I) nx[j] = gImage[x];
         if (j >= 1 || it.c == 0) nd[j] = dsrc0[x];
       }
     }
@@ -204,7 +209,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
           if (max(jlo, it.c == 0 ? 0 : 1) <= jtop)
             __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + 4 * (g0 + wave0), 16, 0, 0);
           if (USE_I && max(jlo, 0) <= jtop)
-            __builtin_amdgcn_global_load_lds(g.image + x, StI + 4 * (g0 + wave0), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(gImage + x, StI + 4 * (g0 + wave0), 16, 0, 0);
         }
       }
     } else {
@@ -221,7 +226,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         if (ok) {
           const int x = k + cpp * g.sp + cqq * g.sq;
           if (j >= 1 || it.c == 0) __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + f0 + wave0, 4, 0, 0);
-          if (USE_I) __builtin_amdgcn_global_load_lds(g.image + x, StI + f0 + wave0, 4, 0, 0);
+          if (USE_I) __builtin_amdgcn_global_load_lds(gImage + x, StI + f0 + wave0, 4, 0, 0);
         }
       }
     }
@@ -347,8 +352,8 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
           if (SCANC)
             Res[own_slot * SCR + i] = best;
           else
-            g.D[x] = best;
-          if (REC && g.rec) g.rec[x] = (uint8_t)choice;
+            gD[x] = best;
+          if (REC && g.rec) gRec[x] = (uint8_t)choice;
           if (i == kk - 1) st64_relaxed(xout + own_slot, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
         }
       }
@@ -368,7 +373,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         const int opp = cur.p0 + own / TQ, oqq = cur.q0 + (own - (own / TQ) * TQ);
         if (i < kk && opp < Np && oqq < Nq) {
           const int t = cur.t0 + i;
-          g.D[(g.sign > 0 ? t : Na - 1 - t) + opp * g.sp + oqq * g.sq] = Res[own * SCR + i];
+          gD[(g.sign > 0 ? t : Na - 1 - t) + opp * g.sp + oqq * g.sq] = Res[own * SCR + i];
         }
       }
       // Res is rewritten only after the next item's staging barrier.

@@ -44,6 +44,18 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return x * base + min(x, extra) + r;
 }
 
+// A pointer into global memory, typed as such.  Pointers read out of a
+// descriptor table in memory (the batched launches) carry no address space,
+// and accesses through them compile to generic FLAT instructions; those also
+// count against the LDS wait counter, so every LDS barrier would then wait for
+// the global stores in flight.
+template <class T>
+using gmem = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gmem<T> to_gmem(T* p) {
+  return (gmem<T>)p;
+}
+
 __device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -127,6 +139,11 @@ template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE, bool REC, int N
 __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                          unsigned long long limit, float* lds, int wg, int G) {
   const PassDesc g = *gp;  // uniform copy: no aliasing with the stores below
+  // global-memory views of the descriptor's arrays
+  const gmem<const float> gImage = to_gmem(g.image);
+  const gmem<const float> gMask = to_gmem(g.mask);
+  const gmem<float> gD = to_gmem(g.D);
+  const gmem<uint8_t> gRec = to_gmem(g.rec);
   using L = Layout<NDIM, TP, TQ, K, SCANC>;
   constexpr int BQ = L::BQ, NB = L::NB, SC = L::SC, SCR = L::SCR, STAGE = L::STAGE;
   const int tid = threadIdx.x;
@@ -158,8 +175,8 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       for (int f = tid; f < rp * rq; f += NT) {
         const int r = f / rq, cq = f - r * rq;
         const int x = kf * g.sa + (p0 + r) * g.sp + (q0 + cq) * g.sq;
-        if (g.init) g.D[x] = g.v * g.mask[x];
-        if (REC && g.rec) g.rec[x] = 0;
+        if (g.init) gD[x] = g.v * gMask[x];
+        if (REC && g.rec) gRec[x] = 0;
       }
     }
   }
@@ -194,7 +211,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
       // plane 0 too in chunk 0 (the pass's unchanged first plane); the image for
       // all planes.
       {
-        const float* dsrc = g.init ? g.mask : g.D;
+        const gmem<const float> dsrc = g.init ? gMask : (gmem<const float>)gD;
         if (!SCANC && vec4) {
           // 16-byte groups of 4 cells along q (the contiguous axis): groups never
           // straddle the plane edge because q0 - K and Nq are multiples of 4.
@@ -213,7 +230,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
               const int x = k * g.sa + pp * g.sp + qq;
               if (j >= 1 || c == 0) __builtin_amdgcn_global_load_lds(dsrc + x, StD + 4 * (g0 + wave0), 16, 0, 0);
               for (int ch = 0; ch < nch; ++ch)
-                __builtin_amdgcn_global_load_lds(g.image + (long long)ch * g.N + x, StI + ch * STAGE + 4 * (g0 + wave0),
+                __builtin_amdgcn_global_load_lds(gImage + (long long)ch * g.N + x, StI + ch * STAGE + 4 * (g0 + wave0),
                                                  16, 0, 0);
             }
           }
@@ -240,7 +257,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
                 __builtin_amdgcn_global_load_lds(dsrc + x, StD + 4 * (g0 + wave0), 16, 0, 0);
               if (max(jlo, 0) <= jtop)
                 for (int ch = 0; ch < nch; ++ch)
-                  __builtin_amdgcn_global_load_lds(g.image + (long long)ch * g.N + x,
+                  __builtin_amdgcn_global_load_lds(gImage + (long long)ch * g.N + x,
                                                    StI + ch * STAGE + 4 * (g0 + wave0), 16, 0, 0);
             }
           }
@@ -267,7 +284,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
               const int x = k * g.sa + pp * g.sp + qq * g.sq;
               if (j >= 1 || c == 0) __builtin_amdgcn_global_load_lds(dsrc + x, StD + f0 + wave0, 4, 0, 0);
               for (int ch = 0; ch < nch; ++ch)
-                __builtin_amdgcn_global_load_lds(g.image + (long long)ch * g.N + x, StI + ch * STAGE + f0 + wave0, 4,
+                __builtin_amdgcn_global_load_lds(gImage + (long long)ch * g.N + x, StI + ch * STAGE + f0 + wave0, 4,
                                                  0, 0);
             }
           }
@@ -432,8 +449,8 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
             if (SCANC)
               Res[own * SCR + i] = best;
             else
-              g.D[x] = best;
-            if (REC && g.rec) g.rec[x] = (uint8_t)choice;
+              gD[x] = best;
+            if (REC && g.rec) gRec[x] = (uint8_t)choice;
             if (i == kk - 1)
               st64_relaxed(xout + own, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
           }
@@ -454,7 +471,7 @@ __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long*
           if (i < kk && r < rp && cq < rq) {
             const int t = t0 + i;
             const int k = g.sign > 0 ? t : Na - 1 - t;
-            g.D[k * g.sa + (p0 + r) * g.sp + (q0 + cq) * g.sq] = Res[f];
+            gD[k * g.sa + (p0 + r) * g.sp + (q0 + cq) * g.sq] = Res[f];
           }
         }
         // Res is rewritten only after the next chunk's first barrier.
