@@ -21,7 +21,7 @@ Also reported (same JSON line):
                 when a summary for the current kernel source exists
   converge      the same volume run to its fixed point (iterations and time)
   configs_2d    the 128^2 and 2048^2 x 3 images, voxel-updates/s per lambda
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample: one
+  cpu_baseline  the CPU oracle (single thread, and OpenMP over each plane) on a bounded sample: one
                 iteration (6 passes) of the same volume
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
@@ -79,8 +79,28 @@ def cpu_baseline(c):
     oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
     dt = time.perf_counter() - t
     vu = c["mask"].size * 6
-    return {"value": vu / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 iteration (6 passes) of the {c['name']} volume, {vu} voxel-updates in {dt:.1f} s"}
+    out = {"value": vu / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"1 iteration (6 passes) of the {c['name']} volume, {vu} voxel-updates in {dt:.1f} s",
+           "cpu": cpu_model()}
+    # The paper's CPU scheme: the same oracle with each plane's voxels shared
+    # among OpenMP threads (OMP_NUM_THREADS, else every host core).
+    t = time.perf_counter()
+    _, threads = oracle.ggdt_omp(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1)
+    dt = time.perf_counter() - t
+    out["openmp"] = {"value": vu / dt, "unit": "voxel-updates/s", "cores": threads,
+                     "sample": f"the same iteration in {dt:.2f} s"}
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def calibrate_copy(mib):

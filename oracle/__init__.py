@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ggdt_ref.c")
 _LIB = os.path.join(_HERE, "libggdt_ref.so")
-_CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+_CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-shared", "-fPIC"]
 
 _lib = None
@@ -109,6 +109,53 @@ def ggdt(image, mask, spacing, v, lam, iterations, precision="f32", records=Fals
             _p(rec) if rec is not None else None)
     _check(rc, "ref_ggdt")
     return (out, rec) if records else out
+
+
+def ggdt_omp(image, mask, spacing, v, lam, iterations):
+    """The FP32 schedule with each plane's voxels shared among OpenMP threads
+    (OMP_NUM_THREADS); same values as ``ggdt(..., "f32")``.  Returns (D, threads)."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    img, m, sp = _f32(image), _f32(mask), _f32(spacing)
+    out = np.empty(spatial, dtype=np.float32)
+    rc = lib.ref_ggdt_f32_omp(len(spatial), _dims(spatial), image.shape[0], _p(img), _p(m), _p(sp),
+                              ctypes.c_float(v), ctypes.c_float(lam), int(iterations), _p(out))
+    if rc < 0:
+        raise RuntimeError(f"ref_ggdt_f32_omp failed with code {rc}")
+    return out, rc
+
+
+# ------------------------------------------------ signed distance and GSF
+# The paper names a signed geodesic distance and the geodesic symmetric filter
+# (GSF) of Criminisi et al. 2008 among what the software computes (sections
+# "Statement of need" and "Implementation") without defining them; these are
+# this project's readings, composed from the FP32 schedule with FP32 pointwise
+# operations.  Object masks use the seed convention: 0 on the object, 1 elsewhere.
+
+def signed(image, mask, spacing, v, lam, iterations):
+    """S = D(I; M) - D(I; 1 - M): negative on the object, positive outside."""
+    m = _f32(mask)
+    d_obj = ggdt(image, m, spacing, v, lam, iterations, "f32")
+    d_bg = ggdt(image, np.float32(1) - m, spacing, v, lam, iterations, "f32")
+    return d_obj - d_bg
+
+
+def object_mask(S, theta):
+    """Mask of the object {x : S(x) < theta}: 0 on it, 1 elsewhere."""
+    return np.where(_f32(S) < np.float32(theta), np.float32(0), np.float32(1))
+
+
+def gsf(image, mask, theta_d, theta_e, spacing, v, lam, iterations):
+    """Geodesic symmetric filter: the closing (dilate by theta_d, then erode by
+    theta_e) and the opening (erode, then dilate) of the object of M, merged
+    through their signed distances: returns (S_d + S_e) + (theta_e - theta_d),
+    where S_d, S_e are the signed distances of the dilated and eroded objects.
+    The filtered object is where the result is negative."""
+    s0 = signed(image, mask, spacing, v, lam, iterations)
+    s_d = signed(image, object_mask(s0, theta_d), spacing, v, lam, iterations)
+    s_e = signed(image, object_mask(s0, -np.float32(theta_e)), spacing, v, lam, iterations)
+    t = np.float32(theta_e) - np.float32(theta_d)
+    return (s_d + s_e) + t
 
 
 def single_pass(image, D, spacing, lam, axis, sign, precision="f32", records=False):

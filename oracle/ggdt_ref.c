@@ -47,6 +47,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define REF_OK 0
 #define REF_EINVAL -1
@@ -194,18 +195,48 @@ static int check_common(int ndim, const int* dims, int C, const void* image, con
 /* One directional pass along axis a in direction sign (+1 / -1), in place on D.
  * rec (nullable) receives one byte per voxel: 0 = keep, 1 + j = parent through
  * offset j of pass_offsets(). */
-static void pass_f32(const grid_t* g, int C, const float* img, const double* sp, float lam,
-                     int a, int sign, float* D, uint8_t* rec) {
-  int delta[9][3];
-  int nd = pass_offsets(g->ndim, a, delta);
-  float A[9];
+/* Update of one voxel x (coordinates xc, on plane k of a pass along axis a):
+ * the keep candidate D(x), then the parents of plane k - sign in offset order. */
+static void update_voxel_f32(const grid_t* g, int C, const float* img, float lam, const float* A,
+                             const int (*delta)[3], int nd, int a, int sign, int k, const int* xc,
+                             float* D, uint8_t* rec) {
+  long cs = g->n;
+  long i = flatten(g, xc);
+  float best = D[i];
+  uint8_t choice = 0;
   for (int j = 0; j < nd; ++j) {
+    int yc[3];
+    for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + delta[j][b];
+    yc[a] = k - sign;
+    if (!in_grid(g, yc)) continue;
+    long y = flatten(g, yc);
+    float w = edge_w_f32(img, cs, C, i, y, lam, A[j]);
+    float cand = D[y] + w;
+    if (cand < best) {
+      best = cand;
+      choice = (uint8_t)(1 + j);
+    }
+  }
+  D[i] = best;
+  if (rec) rec[i] = choice;
+}
+
+static void pass_tables_f32(const grid_t* g, const double* sp, float lam, int a, int (*delta)[3], float* A,
+                            int* nd) {
+  *nd = pass_offsets(g->ndim, a, delta);
+  for (int j = 0; j < *nd; ++j) {
     int dx[3] = {delta[j][0], delta[j][1], delta[j][2]};
     dx[a] = 1;
     A[j] = (float)((1.0 - (double)lam) * spatial_sq(g->ndim, sp, dx));
   }
+}
+
+static void pass_f32(const grid_t* g, int C, const float* img, const double* sp, float lam,
+                     int a, int sign, float* D, uint8_t* rec) {
+  int delta[9][3], nd;
+  float A[9];
+  pass_tables_f32(g, sp, lam, a, delta, A, &nd);
   int Na = g->dims[a];
-  long cs = g->n;
   if (rec) {
     /* the first plane in scan order is never modified */
     plane_it pf;
@@ -216,26 +247,37 @@ static void pass_f32(const grid_t* g, int C, const float* img, const double* sp,
     int k = sign > 0 ? t : Na - 1 - t;
     /* all voxels of plane k; they read plane k - sign only */
     plane_it pi;
-    for (plane_first(&pi, g, a, k); !pi.done; plane_next(&pi)) {
-      const int* xc = pi.xc;
-      long i = flatten(g, xc);
-      float best = D[i];
-      uint8_t choice = 0;
-      for (int j = 0; j < nd; ++j) {
-        int yc[3];
-        for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + delta[j][b];
-        yc[a] = k - sign;
-        if (!in_grid(g, yc)) continue;
-        long y = flatten(g, yc);
-        float w = edge_w_f32(img, cs, C, i, y, lam, A[j]);
-        float cand = D[y] + w;
-        if (cand < best) {
-          best = cand;
-          choice = (uint8_t)(1 + j);
-        }
+    for (plane_first(&pi, g, a, k); !pi.done; plane_next(&pi))
+      update_voxel_f32(g, C, img, lam, A, (const int (*)[3])delta, nd, a, sign, k, pi.xc, D, rec);
+  }
+}
+
+/* The same pass with the voxels of each plane shared among OpenMP threads (the
+ * paper's CPU parallelisation: a plane's voxels only read the previous plane, so
+ * any order gives the same values). */
+static void pass_f32_omp(const grid_t* g, int C, const float* img, const double* sp, float lam,
+                         int a, int sign, float* D) {
+  int delta[9][3], nd;
+  float A[9];
+  pass_tables_f32(g, sp, lam, a, delta, A, &nd);
+  int Na = g->dims[a];
+  int o[2] = {0, 0}, no = 0;
+  for (int b = 0; b < g->ndim; ++b)
+    if (b != a) o[no++] = b;
+  long P = 1;
+  for (int i = 0; i < no; ++i) P *= g->dims[o[i]];
+  for (int t = 1; t < Na; ++t) {
+    int k = sign > 0 ? t : Na - 1 - t;
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < P; ++m) {
+      int xc[3] = {0, 0, 0};
+      long r = m;
+      for (int i = no - 1; i >= 0; --i) {
+        xc[o[i]] = (int)(r % g->dims[o[i]]);
+        r /= g->dims[o[i]];
       }
-      D[i] = best;
-      if (rec) rec[i] = choice;
+      xc[a] = k;
+      update_voxel_f32(g, C, img, lam, A, (const int (*)[3])delta, nd, a, sign, k, xc, D, NULL);
     }
   }
 }
@@ -305,6 +347,28 @@ int ref_ggdt_f32(int ndim, const int* dims, int C, const float* image, const flo
       for (int s = 0; s < 2; ++s, ++p)
         pass_f32(&g, C, image, sp, lam, a, s == 0 ? +1 : -1, out, records ? records + (long)p * g.n : NULL);
   return REF_OK;
+}
+
+/* ref_ggdt_f32 with every plane's voxels shared among OpenMP threads; same
+ * result.  Returns the number of threads used, or a negative error. */
+int ref_ggdt_f32_omp(int ndim, const int* dims, int C, const float* image, const float* mask,
+                     const float* spacing, float v, float lam, int iterations, float* out) {
+  grid_t g;
+  int e = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (e) return e;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  for (int it = 0; it < iterations; ++it)
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s) pass_f32_omp(&g, C, image, sp, lam, a, s == 0 ? +1 : -1, out);
+  int nt = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    nt = omp_get_num_threads();
+  }
+  return nt;
 }
 
 int ref_ggdt_f64(int ndim, const int* dims, int C, const double* image, const double* mask,

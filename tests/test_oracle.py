@@ -258,6 +258,17 @@ def test_iterations_zero_and_unit_dims():
     assert np.array_equal(D[0], np.arange(6, dtype=np.float32))
 
 
+@pytest.mark.parametrize("shape,C,lam", [((17, 23, 9), 1, 0.6), ((31, 40), 3, 1.0), ((12, 7, 15), 2, 0.0),
+                                         ((1, 9, 5), 1, 0.4)])
+def test_plane_parallel_schedule_equals_serial(shape, C, lam):
+    """The OpenMP form (voxels of a plane shared among threads) gives the serial values bit for bit."""
+    c = synth.small_case(shape, C=C, seed=5, lam=lam, iterations=2)
+    ref = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 2, "f32")
+    got, threads = oracle.ggdt_omp(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 2)
+    assert threads >= 1
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
 # ------------------------------------------------- the lambda = 1 fast-path identity
 
 def test_sqrt_of_square_is_abs_exhaustive():
