@@ -299,6 +299,44 @@ def bench_backward(reps):
                          "note": "batched backward launch, algorithmic bytes"}}
 
 
+def bench_composed(c, reps):
+    """Signed distance (2 transforms) and geodesic symmetric filter (6) of the
+    benchmark volume; voxel-updates count every pass of every transform."""
+    import numpy as np
+    import torch
+    from paper_2208_00001_amd import binding as B
+    dev = "cuda:0"
+    shape = c["mask"].shape
+    img = torch.from_numpy(c["image"]).to(dev)
+    m = torch.from_numpy(c["mask"]).to(dev)
+    out = torch.empty(shape, dtype=torch.float32, device=dev)
+    lib = B.load_library()
+    dims = B._dims(shape)
+    vu1 = int(np.prod(shape)) * 6 * c["iterations"]
+    res = {"workload": f"{c['name']}, signed distance and GSF (theta_d 8, theta_e 4)"}
+    for kind, q, ntr, run in (
+            ("signed", lib.ggdt_signed_workspace_bytes, 2,
+             lambda ws: B.ggdt_signed(img, m, c["spacing"], c["v"], c["lam"], c["iterations"], out=out,
+                                      workspace=ws)),
+            ("gsf", lib.ggdt_gsf_workspace_bytes, 6,
+             lambda ws: B.ggdt_gsf(img, m, 8.0, 4.0, c["spacing"], c["v"], c["lam"], c["iterations"], out=out,
+                                   workspace=ws))):
+        ws = torch.empty(int(q(3, dims, 1)), dtype=torch.uint8, device=dev)
+        run(ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run(ws)
+        b.record()
+        torch.cuda.synchronize()
+        assert B.workspace_status(ws) == 0, f"watchdog fired ({kind})"
+        ms = a.elapsed_time(b) / reps
+        res[kind] = {"ms": ms, "transforms": ntr, "ms_per_transform": ms / ntr,
+                     "value": ntr * vu1 / (ms * 1e-3), "unit": "voxel-updates/s"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +431,7 @@ def main():
         line["configs_2d"] = bench_small_configs()
         line["batched"] = bench_batched(max(3, min(args.steps, 10)))
         line["backward"] = bench_backward(max(3, min(args.steps, 10)))
+        line["composed"] = bench_composed(c, 3)
     if args.calibrate_copy > 0:
         line["calibration"] = calibrate_copy(args.calibrate_copy)
     if not args.no_cpu_baseline:

@@ -148,6 +148,44 @@ int ggdt3d_backward(const float* image, const uint8_t* records, const float* gra
                     float* grad_softmask, int C, int D, int H, int W, void* workspace,
                     size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------ signed distance and GSF
+ * The paper lists a signed geodesic distance and the geodesic symmetric filter
+ * (GSF, after Criminisi et al. 2008) among what the software computes (sections
+ * "Statement of need" and "Implementation") but does not define them.  This
+ * library's reading, composed from the transform above (same schedule and FP32
+ * arithmetic) and FP32 pointwise steps:
+ *   S(M)  = D(I; M) - D(I; 1 - M)      negative where M marks the object (M = 0)
+ *   obj(S, t) = mask of {x : S(x) < t}  (0 on the set, 1 elsewhere)
+ *   GSF   = (S(obj(S0, theta_d)) + S(obj(S0, -theta_e))) + (theta_e - theta_d),
+ *           S0 = S(M): the closing (dilate by theta_d, erode by theta_e) and the
+ *           opening (erode, then dilate) merged through their signed distances;
+ *           the filtered object is {GSF < 0}.
+ * theta_e - theta_d is rounded to FP32 once.  Shapes, layouts, streams and
+ * errors as ggdt2d/ggdt3d; out must not overlap image, softmask or the
+ * workspace.  theta_d, theta_e must be finite and >= 0 (else
+ * GGDT_ERR_BAD_PARAM). */
+
+/* Workspace bytes: the transform's workspace plus 2 (signed) or 4 (GSF) fp32
+ * buffers of prod(dims) values.  0 for invalid shapes. */
+size_t ggdt_signed_workspace_bytes(int ndim, const int* dims, int C);
+size_t ggdt_gsf_workspace_bytes(int ndim, const int* dims, int C);
+
+/* out = S(M) with `iterations` iterations for both transforms. */
+int ggdt2d_signed(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                  int iterations, float* out, int C, int H, int W, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream);
+int ggdt3d_signed(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                  int iterations, float* out, int C, int D, int H, int W, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
+/* out = GSF (six transforms, `iterations` iterations each). */
+int ggdt2d_gsf(const float* image, const float* softmask, const float* spacing, float theta_d, float theta_e,
+               float v, float lambda, int iterations, float* out, int C, int H, int W, void* workspace,
+               size_t workspace_bytes, hipStream_t stream);
+int ggdt3d_gsf(const float* image, const float* softmask, const float* spacing, float theta_d, float theta_e,
+               float v, float lambda, int iterations, float* out, int C, int D, int H, int W, void* workspace,
+               size_t workspace_bytes, hipStream_t stream);
+
 /* After the stream has finished a call, report whether its inter-workgroup waits
  * all completed: synchronises `stream`, returns GGDT_OK or GGDT_ERR_WATCHDOG (the
  * results of that call are then invalid).  `workspace` is the one the call used. */

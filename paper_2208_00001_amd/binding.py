@@ -61,6 +61,16 @@ _SIGS = {
                                  _c_size, _vp]),
     "ggdt3d_converge": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
                                  _vp, _c_size, _vp]),
+    "ggdt_signed_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt_gsf_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt2d_signed": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp, _c_size,
+                               _vp]),
+    "ggdt3d_signed": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int, _vp,
+                               _c_size, _vp]),
+    "ggdt2d_gsf": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_float, _c_float, _c_int, _vp, _c_int, _c_int,
+                            _c_int, _vp, _c_size, _vp]),
+    "ggdt3d_gsf": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_float, _c_float, _c_int, _vp, _c_int, _c_int,
+                            _c_int, _c_int, _vp, _c_size, _vp]),
     "ggdt_workspace_iterations": (_c_int, [_vp, _vp, _vp]),
     "ggdt_workspace_status": (_c_int, [_vp, _vp]),
     "ggdt_set_spin_limit": (None, [ctypes.c_ulonglong]),
@@ -196,6 +206,36 @@ def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100
     if rc != GGDT_OK:
         raise GGDTError(rc, "ggdt_workspace_iterations")
     return out, n.value
+
+
+def _composed(kind, image, softmask, spacing, v, lamb, iterations, thetas, out, workspace):
+    lib = load_library()
+    image, softmask, spatial = _prep(image, softmask)
+    nd, C = len(spatial), image.shape[0]
+    if out is None:
+        out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    if workspace is None:
+        q = lib.ggdt_signed_workspace_bytes if kind == "signed" else lib.ggdt_gsf_workspace_bytes
+        n = int(q(nd, _dims(spatial), C))
+        if n == 0:
+            raise ValueError(f"invalid shape {tuple(spatial)} with C={C}")
+        workspace = torch.empty(n, dtype=torch.uint8, device=softmask.device)
+    fn = getattr(lib, f"ggdt{nd}d_{kind}")
+    rc = fn(_ptr(image), _ptr(softmask), _spacing(spacing, nd), *[float(t) for t in thetas], float(v), float(lamb),
+            int(iterations), _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    return out
+
+
+def ggdt_signed(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
+    """Signed distance D(I; M) - D(I; 1 - M) (2D or 3D by the mask's rank)."""
+    return _composed("signed", image, softmask, spacing, v, lamb, iterations, (), out, workspace)
+
+
+def ggdt_gsf(image, softmask, theta_d, theta_e, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
+    """Geodesic symmetric filter (S_d + S_e) + (theta_e - theta_d); the filtered object is where it is < 0."""
+    return _composed("gsf", image, softmask, spacing, v, lamb, iterations, (theta_d, theta_e), out, workspace)
 
 
 def ggdt_forward_rec(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, records=None,

@@ -55,5 +55,10 @@ int max_tiles(const Problem& pr, const Tuning& tu);
 int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,
                    float* gI, int p, int K, unsigned epoch_base, BwdDesc* d);
 size_t workspace_for(const Problem& pr, const Tuning& tu);
+// Enqueue the whole forward schedule of one instance on `stream` (arguments
+// already validated; ws holds at least workspace_for(pr, tu) bytes).
+int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
+                    float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
+                    hipStream_t stream);
 
 }  // namespace ggdt

@@ -168,4 +168,14 @@ hipError_t launch_classify(const float* image, long long n, unsigned* words, hip
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream);
 hipError_t launch_iteration_end(unsigned* words, int it, hipStream_t stream);
 
+// Pointwise steps of the signed distance and the geodesic symmetric filter
+// (compose.hip), FP32, element i of n:
+//   kOpComplement  out = 1 - a
+//   kOpObjectMask  out = a < s ? 0 : 1
+//   kOpSub         out = a - b
+//   kOpSumShift    out = (a + b) + s
+enum ComposeOp { kOpComplement = 0, kOpObjectMask = 1, kOpSub = 2, kOpSumShift = 3 };
+hipError_t launch_compose(int op, const float* a, const float* b, float s, float* out, long long n,
+                          hipStream_t stream);
+
 }  // namespace ggdt

@@ -34,7 +34,8 @@ def test_header_declares_expected_entry_points():
     for n in ["ggdt2d", "ggdt3d", "ggdt_workspace_bytes", "ggdt_records_bytes", "ggdt2d_forward_rec",
               "ggdt3d_forward_rec", "ggdt2d_backward", "ggdt3d_backward", "ggdt_batched_plan", "ggdt_batched_run",
               "ggdt_batched_backward", "ggdt_plan_destroy", "ggdt_strerror", "ggdt_workspace_status",
-              "ggdt_set_spin_limit"]:
+              "ggdt_set_spin_limit", "ggdt2d_signed", "ggdt3d_signed", "ggdt2d_gsf", "ggdt3d_gsf",
+              "ggdt_signed_workspace_bytes", "ggdt_gsf_workspace_bytes"]:
         assert n in names, n
 
 
@@ -100,3 +101,38 @@ def test_valid_call_without_device_is_not_a_validation_error(lib):
         pytest.skip("would launch on fake pointers when a GPU is present")
     rc = call3d(lib)
     assert rc in (-5, -8, 0)  # no GPU here: HIP error / unsupported device
+
+
+def test_composed_workspace_sizes(lib):
+    dims = (ctypes.c_int * 3)(64, 48, 40)
+    base = lib.ggdt_workspace_bytes(3, dims, 2)
+    n = 64 * 48 * 40 * 4
+    assert lib.ggdt_signed_workspace_bytes(3, dims, 2) >= base + 2 * n
+    assert lib.ggdt_gsf_workspace_bytes(3, dims, 2) >= base + 4 * n
+    bad = (ctypes.c_int * 3)(0, 4, 4)
+    assert lib.ggdt_signed_workspace_bytes(3, bad, 1) == 0
+    assert lib.ggdt_gsf_workspace_bytes(3, dims, 0) == 0
+
+
+def call_gsf3d(lib, theta_d=1.0, theta_e=0.5, out=FAKE + (2 << 30), wsb=1 << 30, lam=0.5):
+    sp = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    return lib.ggdt3d_gsf(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + (1 << 30)), sp, theta_d, theta_e, 1e10, lam,
+                          2, ctypes.c_void_p(out), 1, 8, 8, 8, ctypes.c_void_p(FAKE + (3 << 30)), wsb, None)
+
+
+def test_composed_validation_codes(lib):
+    assert call_gsf3d(lib, theta_d=-1.0) == -3
+    assert call_gsf3d(lib, theta_e=float("nan")) == -3
+    assert call_gsf3d(lib, theta_d=float("inf")) == -3
+    assert call_gsf3d(lib, lam=2.0) == -3
+    assert call_gsf3d(lib, wsb=1024) == -4
+    assert call_gsf3d(lib, out=FAKE + 64) == -7
+    sp = (ctypes.c_float * 2)(1.0, 1.0)
+    dims_ws = lib.ggdt_workspace_bytes(2, (ctypes.c_int * 2)(8, 8), 1)
+    # the transform's own workspace is too small for the signed distance's buffers
+    assert lib.ggdt2d_signed(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + (1 << 30)), sp, 1e10, 1.0, 2,
+                             ctypes.c_void_p(FAKE + (2 << 30)), 1, 8, 8, ctypes.c_void_p(FAKE + (3 << 30)), dims_ws,
+                             None) == -4
+    assert lib.ggdt2d_signed(None, ctypes.c_void_p(FAKE + (1 << 30)), sp, 1e10, 1.0, 2,
+                             ctypes.c_void_p(FAKE + (2 << 30)), 1, 8, 8, ctypes.c_void_p(FAKE + (3 << 30)), 1 << 30,
+                             None) == -1
