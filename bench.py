@@ -89,7 +89,31 @@ def cpu_baseline(c):
     dt = time.perf_counter() - t
     out["openmp"] = {"value": vu / dt, "unit": "voxel-updates/s", "cores": threads,
                      "sample": f"the same iteration in {dt:.2f} s"}
+    out["toivanen"] = toivanen_comparison(c)
     return out
+
+
+def toivanen_comparison(c):
+    """Toivanen's sequential raster scan (the paper's comparison method, one
+    thread): its rate on one iteration of the volume (two raster sweeps over
+    half of the 26-neighbourhood), and the iterations each method needs to
+    reach its fixed point on smaller synthetic inputs."""
+    import oracle
+    from paper_2208_00001_amd import synth
+    t = time.perf_counter()
+    oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
+    dt = time.perf_counter() - t
+    res = {"voxel_visits_per_s": 2 * c["mask"].size / dt, "cores": 1,
+           "sample": f"1 iteration (2 sweeps) of the {c['name']} volume in {dt:.1f} s", "iterations_to_fixed_point": {}}
+    for cc in (synth.config1(1.0), synth.config1(0.0), synth.config3(size=64)):
+        _, n_scan = oracle.until_converged(cc["image"], cc["mask"], cc["spacing"], cc["v"], cc["lam"])
+        _, n_toiv = oracle.toivanen(cc["image"], cc["mask"], cc["spacing"], cc["v"], cc["lam"], 10000, "f32",
+                                    converge=True)
+        nd = cc["mask"].ndim
+        res["iterations_to_fixed_point"][cc["name"]] = {
+            "directional_scan": n_scan, "directional_passes": n_scan * 2 * nd,
+            "toivanen": n_toiv, "toivanen_sweeps": n_toiv * 2}
+    return res
 
 
 def cpu_model():

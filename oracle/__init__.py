@@ -198,6 +198,33 @@ def until_converged(image, mask, spacing, v, lam, max_iterations=10000, precisio
     return out, n
 
 
+def toivanen(image, mask, spacing, v, lam, iterations, precision="f32", converge=False):
+    """Toivanen's sequential raster scan (forward then backward raster sweep per
+    iteration, in-place updates over the preceding half of the 8/26-neighbourhood).
+    converge=False: exactly `iterations` iterations, returns D.  converge=True:
+    until an iteration changes nothing (at most `iterations`), returns (D, n)."""
+    lib = _load()
+    image, spatial = _split(image, mask)
+    C = image.shape[0]
+    if precision == "f32":
+        img, m, sp = _f32(image), _f32(mask), _f32(spacing)
+        out = np.empty(spatial, dtype=np.float32)
+        n = lib.ref_toivanen_f32(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp), ctypes.c_float(v),
+                                 ctypes.c_float(lam), int(iterations), int(converge), _p(out))
+    else:
+        img, m, sp = _f64(image), _f64(mask), _f64(spacing)
+        out = np.empty(spatial, dtype=np.float64)
+        n = lib.ref_toivanen_f64(len(spatial), _dims(spatial), C, _p(img), _p(m), _p(sp), ctypes.c_double(v),
+                                 ctypes.c_double(lam), int(iterations), int(converge), _p(out))
+    if n < 0 and not (converge and n == -1):
+        raise RuntimeError(f"ref_toivanen failed with code {n}")
+    if converge:
+        if n < 0:
+            raise RuntimeError(f"did not converge within {iterations} iterations")
+        return out, n
+    return out
+
+
 def dijkstra(image, mask, spacing, v, lam, precision="f64"):
     """Multi-source Dijkstra on the 8/26-connected grid with the same edge cost."""
     lib = _load()

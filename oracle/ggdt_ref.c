@@ -413,6 +413,141 @@ int ref_pass_f64(int ndim, const int* dims, int C, const double* image, const do
 /* Iterate whole iterations until one changes no voxel bitwise (at most
  * max_iterations).  Returns the number of iterations after which the state was
  * already fixed, or -1 if the cap was hit; out holds the final state. */
+/* ------------------------------------------- Toivanen's sequential raster scan
+ * The paper's software also ships the sequential raster-scan transform of
+ * Toivanen (1996) for comparison (section "Implementation"), run on one CPU
+ * thread.  Reading used here: one iteration is a forward sweep over the voxels
+ * in raster order (row-major, every axis ascending) followed by a backward
+ * sweep in the reverse order; a voxel takes the minimum of its own value and
+ * D(y) + w(x, y) over the neighbours y of the 8/26-neighbourhood that precede it
+ * in the sweep's order (4 in 2D, 13 in 3D), updating D in place, so it sees the
+ * values already lowered earlier in the same sweep.  Edge costs as in the
+ * passes: w = sqrt((1 - lam) |x - y|_s^2 + lam |I(x) - I(y)|^2). */
+
+/* Offsets y - x of the neighbours preceding x in the forward raster order
+ * (first non-zero component negative); the backward sweep uses their negatives. */
+static int causal_offsets(int ndim, int (*off)[3]) {
+  int n = 0;
+  for (int dz = (ndim == 3 ? -1 : 0); dz <= (ndim == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int d[3] = {0, 0, 0};
+        if (ndim == 3) {
+          d[0] = dz; d[1] = dy; d[2] = dx;
+        } else {
+          d[0] = dy; d[1] = dx;
+        }
+        int first = 0;
+        for (int b = 0; b < ndim && first == 0; ++b) first = d[b];
+        if (first < 0) {
+          off[n][0] = d[0]; off[n][1] = d[1]; off[n][2] = d[2];
+          ++n;
+        }
+      }
+  return n;
+}
+
+static void toivanen_sweep_f32(const grid_t* g, int C, const float* img, const double* sp, float lam, int dir,
+                               float* D) {
+  int off[13][3];
+  int no = causal_offsets(g->ndim, off);
+  float A[13];
+  for (int j = 0; j < no; ++j) {
+    int dx[3] = {abs(off[j][0]), abs(off[j][1]), abs(off[j][2])};
+    A[j] = (float)((1.0 - (double)lam) * spatial_sq(g->ndim, sp, dx));
+  }
+  for (long t = 0; t < g->n; ++t) {
+    long i = dir > 0 ? t : g->n - 1 - t;
+    int xc[3] = {0, 0, 0};
+    unflatten(g, i, xc);
+    float best = D[i];
+    for (int j = 0; j < no; ++j) {
+      int yc[3];
+      for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + dir * off[j][b];
+      if (!in_grid(g, yc)) continue;
+      long y = flatten(g, yc);
+      float cand = D[y] + edge_w_f32(img, g->n, C, i, y, lam, A[j]);
+      if (cand < best) best = cand;
+    }
+    D[i] = best;
+  }
+}
+
+static void toivanen_sweep_f64(const grid_t* g, int C, const double* img, const double* sp, double lam, int dir,
+                               double* D) {
+  int off[13][3];
+  int no = causal_offsets(g->ndim, off);
+  double A[13];
+  for (int j = 0; j < no; ++j) {
+    int dx[3] = {abs(off[j][0]), abs(off[j][1]), abs(off[j][2])};
+    A[j] = (1.0 - lam) * spatial_sq(g->ndim, sp, dx);
+  }
+  for (long t = 0; t < g->n; ++t) {
+    long i = dir > 0 ? t : g->n - 1 - t;
+    int xc[3] = {0, 0, 0};
+    unflatten(g, i, xc);
+    double best = D[i];
+    for (int j = 0; j < no; ++j) {
+      int yc[3];
+      for (int b = 0; b < g->ndim; ++b) yc[b] = xc[b] + dir * off[j][b];
+      if (!in_grid(g, yc)) continue;
+      long y = flatten(g, yc);
+      double cand = D[y] + edge_w_f64(img, g->n, C, i, y, lam, A[j]);
+      if (cand < best) best = cand;
+    }
+    D[i] = best;
+  }
+}
+
+/* Toivanen's transform.  converge == 0: exactly `iterations` iterations,
+ * returns 0.  converge != 0: iterations until one changes nothing (at most
+ * `iterations`), returns the number that changed some value, or -1. */
+int ref_toivanen_f32(int ndim, const int* dims, int C, const float* image, const float* mask,
+                     const float* spacing, float v, float lam, int iterations, int converge, float* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (rc) return rc;
+  double sp[3];
+  for (int b = 0; b < ndim; ++b) sp[b] = (double)spacing[b];
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  float* prev = converge ? (float*)malloc(sizeof(float) * g.n) : NULL;
+  if (converge && !prev) return REF_ENOMEM;
+  int result = converge ? -1 : 0;
+  for (int it = 1; it <= iterations; ++it) {
+    if (prev) memcpy(prev, out, sizeof(float) * g.n);
+    toivanen_sweep_f32(&g, C, image, sp, lam, +1, out);
+    toivanen_sweep_f32(&g, C, image, sp, lam, -1, out);
+    if (prev && memcmp(prev, out, sizeof(float) * g.n) == 0) {
+      result = it - 1;
+      break;
+    }
+  }
+  free(prev);
+  return result;
+}
+
+int ref_toivanen_f64(int ndim, const int* dims, int C, const double* image, const double* mask,
+                     const double* spacing, double v, double lam, int iterations, int converge, double* out) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (rc) return rc;
+  for (long i = 0; i < g.n; ++i) out[i] = v * mask[i];
+  double* prev = converge ? (double*)malloc(sizeof(double) * g.n) : NULL;
+  if (converge && !prev) return REF_ENOMEM;
+  int result = converge ? -1 : 0;
+  for (int it = 1; it <= iterations; ++it) {
+    if (prev) memcpy(prev, out, sizeof(double) * g.n);
+    toivanen_sweep_f64(&g, C, image, spacing, lam, +1, out);
+    toivanen_sweep_f64(&g, C, image, spacing, lam, -1, out);
+    if (prev && memcmp(prev, out, sizeof(double) * g.n) == 0) {
+      result = it - 1;
+      break;
+    }
+  }
+  free(prev);
+  return result;
+}
+
 int ref_ggdt_until_converged_f32(int ndim, const int* dims, int C, const float* image,
                                  const float* mask, const float* spacing, float v, float lam,
                                  int max_iterations, float* out) {

@@ -11,7 +11,10 @@ mathematics fixes:
     evaluates every target on its own (no sweeping);
   * invariants (seeds stay 0, 0 <= D <= v*M, monotone passes, scan >= Dijkstra,
     fixed-point condition, flip symmetry at convergence);
-  * reverse-mode gradients against central finite differences.
+  * reverse-mode gradients against central finite differences;
+  * the OpenMP form of the schedule against the serial one (bitwise);
+  * Toivanen's sequential raster scan (the paper's comparison method): hand-
+    worked sweeps, convergence to Dijkstra bitwise, monotone iterations.
 """
 import json
 import math
@@ -370,3 +373,53 @@ def test_backward_lambda0_has_no_image_gradient():
     assert np.all(gI == 0)
     # every voxel's value is v*M of exactly one source, so the mask gradient sums to v * sum(W)
     assert math.isclose(gM.sum(), c["v"] * W.sum(), rel_tol=1e-12)
+
+
+# ------------------------------------------- Toivanen's sequential raster scan
+
+def test_toivanen_hand_worked():
+    """lambda = 0, unit spacing: edges cost 1 along an axis, sqrt(2) diagonally."""
+    r = math.sqrt(2.0)
+    m = np.ones((1, 6), np.float64)
+    m[0, 0] = 0
+    D = oracle.toivanen(np.zeros((1, 1, 6)), m, (1, 1), 1e10, 0.0, 1, "f64")
+    assert np.array_equal(D[0], np.arange(6.0))  # one forward sweep carries the seed along the row
+    # seed at the top-left corner: every shortest path runs down/right, the forward sweep finds them all
+    m = np.ones((3, 3))
+    m[0, 0] = 0
+    D = oracle.toivanen(np.zeros((1, 3, 3)), m, (1, 1), 1e10, 0.0, 1, "f64")
+    np.testing.assert_allclose(D, [[0, 1, 2], [1, r, 1 + r], [2, 1 + r, 2 * r]], rtol=1e-15)
+    # seed at the centre: the forward sweep reaches its right and lower neighbours, the backward the rest
+    m = np.ones((3, 3))
+    m[1, 1] = 0
+    D, n = oracle.toivanen(np.zeros((1, 3, 3)), m, (1, 1), 1e10, 0.0, 10, "f64", converge=True)
+    np.testing.assert_allclose(D, [[r, 1, r], [1, 0, 1], [r, 1, r]], rtol=1e-15)
+    assert n == 1
+    # seed at the bottom-right: nothing precedes it in the forward sweep, the backward sweep does everything
+    m = np.ones((2, 3))
+    m[1, 2] = 0
+    D = oracle.toivanen(np.zeros((1, 2, 3)), m, (1, 1), 1e10, 0.0, 1, "f64")
+    np.testing.assert_allclose(D, [[1 + r, r, 1], [2, 1, 0]], rtol=1e-15)
+
+
+@pytest.mark.parametrize("shape,C,lam,soft", [((23, 31), 1, 1.0, False), ((20, 17), 2, 0.5, True),
+                                              ((9, 11, 8), 1, 0.7, False), ((7, 6, 9), 1, 1.0, True),
+                                              ((1, 12, 10), 1, 0.0, False)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_toivanen_converges_to_dijkstra(shape, C, lam, soft, precision):
+    c = synth.small_case(shape, C=C, seed=61, lam=lam, soft=soft, v=4.0 if soft else 1e10)
+    D, _ = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], lam, 1000, precision, converge=True)
+    ref = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], lam, precision=precision)
+    assert np.array_equal(D, ref)
+
+
+def test_toivanen_iterations_monotone_and_above_dijkstra():
+    c = synth.small_case((14, 12, 9), C=1, seed=62, lam=0.8)
+    ref = oracle.dijkstra(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], precision="f64")
+    prev = None
+    for it in range(4):
+        D = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], it, "f64")
+        assert np.all(D >= ref)
+        if prev is not None:
+            assert np.all(D <= prev)
+        prev = D
