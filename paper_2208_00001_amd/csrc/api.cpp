@@ -208,6 +208,19 @@ size_t workspace_for(const Problem& pr, const Tuning& tu) {
   return (size_t)kHeaderWords * 4 + xbuf;
 }
 
+// 2D passes of images with up to kRowMaxC channels run on the row kernel
+// (one wave per 32-cell tile, chunks of 16 rows).  Its exchange area,
+// ceil(Nq / 32) * 32 words per parity, fits in the tile kernel's.
+static void use_row_geometry(const Problem& pr, PassDesc* d) {
+  if (pr.ndim != 2 || pr.C > kRowMaxC) return;
+  d->TP = 1;
+  d->TQ = kRowTQ;
+  d->K = kRowK;
+  d->ntp = 1;
+  d->ntq = (d->Nq + kRowTQ - 1) / kRowTQ;
+  d->nchunk = (d->Na - 1 + kRowK - 1) / kRowK;
+}
+
 // Enqueue the whole forward schedule of one instance.
 int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
@@ -228,6 +241,7 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
     PassDesc d;
     const int rc = build_pass(pr, image, mask, spacing, v, lam, out, records, p, base, &d);
     if (rc) return rc;
+    use_row_geometry(pr, &d);
     d.xbuf = xbuf;
     base += (unsigned)d.nchunk + 1u;
     if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
@@ -300,6 +314,7 @@ int converge_entry(int ndim, const int* dims, int C, const float* image, const f
       PassDesc d;
       rc = build_pass(pr, image, mask, spacing, v, lam, out, nullptr, (it - 1) * per + k, base, &d);
       if (rc) return rc;
+      use_row_geometry(pr, &d);
       d.xbuf = xbuf;
       d.converge = 1;
       base += (unsigned)d.nchunk + 1u;

@@ -3,6 +3,7 @@
 // kernels (workspace reset, image classification, v * M).
 #include "pass_cell.h"
 #include "pass_device.h"
+#include "pass_row.h"
 
 namespace ggdt {
 namespace {
@@ -39,7 +40,38 @@ __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, uns
                                         xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// 2D passes of images with up to kRowMaxC channels: one wave per 32-cell tile.
+template <int RMODE, int NCH, bool REC>
+__global__ __launch_bounds__(kRowLanes) void pass_row_kernel(PassDesc g, unsigned* words, unsigned long long limit) {
+  if (ld_relaxed(words + kWordAbort) != 0u) return;
+  if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
+  run_pass_row_mode<RMODE, NCH, REC>(&g, g.xbuf, words, words + kWordClass, limit, xcd_remap(blockIdx.x, gridDim.x),
+                                     gridDim.x);
+}
+
 using PassKernel = void (*)(PassDesc, unsigned*, unsigned long long);
+
+bool use_row_path(const PassDesc& d, int ndim) {
+  return ndim == 2 && d.TP == 1 && d.TQ == kRowTQ && d.K == kRowK && d.C >= 1 && d.C <= kRowMaxC && d.ntp == 1;
+}
+
+template <int NCH, bool REC>
+PassKernel select_row_mode(int mode) {
+  if (mode == kModeLam0) return pass_row_kernel<kModeLam0, NCH, REC>;
+  if (NCH == 1 && mode == kModeLam1C1) return pass_row_kernel<kModeLam1C1, 1, REC>;
+  return pass_row_kernel<kModeGeneral, NCH, REC>;
+}
+
+template <bool REC>
+PassKernel select_row_channels(const PassDesc& d) {
+  if (d.C == 1) return select_row_mode<1, REC>(d.mode);
+  if (d.C == 2) return select_row_mode<2, REC>(d.mode);
+  return select_row_mode<3, REC>(d.mode);
+}
+
+PassKernel select_row_kernel(const PassDesc& d) {
+  return d.rec ? select_row_channels<true>(d) : select_row_channels<false>(d);
+}
 
 bool use_cell_path(const PassDesc& d, int ndim) {
   return ndim == 3 && d.C == 1 && d.TP == kCellTP && d.TQ == kCellTQ && d.K == kCellK;
@@ -200,6 +232,14 @@ int pass_chunk_for(int ndim, int C, bool scan_contiguous) {
 
 hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned long long spin_limit,
                        hipStream_t stream) {
+  if (use_row_path(d, ndim)) {
+    PassKernel fn = select_row_kernel(d);
+    const int cap = capacity_for(fn, 0, kRowLanes);
+    if (cap <= 0) return hipErrorInvalidConfiguration;
+    const int grid = d.ntq < cap ? d.ntq : cap;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kRowLanes), 0, stream, d, words, spin_limit);
+    return hipGetLastError();
+  }
   if (use_cell_path(d, ndim)) {
     PassKernel fn = select_cell_kernel(d);
     const int cap = capacity_for(fn, 0, kCellThreads);

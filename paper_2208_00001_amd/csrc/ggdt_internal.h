@@ -125,6 +125,9 @@ struct BatchInst {
 
 // Tile geometry of the batched kernels (3D plane tile TP3 x TQ3, 2D row tile TQ2).
 constexpr int kTP3 = 16, kTQ3 = 16, kTQ2 = 256;
+// 2D row kernel (pass_row.h): one 64-lane wave per tile, chunks of kRowK rows,
+// kRowTQ = 64 - 2 kRowK owned cells per tile, images of up to kRowMaxC channels.
+constexpr int kRowLanes = 64, kRowK = 16, kRowTQ = kRowLanes - 2 * kRowK, kRowMaxC = 3;
 
 // Chunk lengths of the two batched kernel classes: class 0 for single-channel
 // batches, class 1 for up to 4 channels.

@@ -56,6 +56,9 @@ SMALL_2D = [
     ((300, 530), 1, 0.6, 2), ((257, 1), 1, 0.5, 2), ((1, 700), 1, 1.0, 2), ((600, 300), 3, 0.5, 1),
     ((128, 128), 2, 1.0, 2), ((517, 263), 1, 0.0, 2), ((333, 777), 1, 1.0, 3), ((64, 1030), 2, 0.25, 2),
     ((2, 2), 1, 0.9, 1), ((1, 1), 1, 0.5, 2),
+    # row kernel (one wave per 32-cell tile, chunks of 16 rows): chunk and tile boundaries
+    ((17, 33), 1, 0.5, 2), ((18, 32), 2, 1.0, 2), ((33, 65), 3, 0.7, 2), ((16, 64), 1, 0.0, 1),
+    ((40, 50), 4, 0.6, 2),  # four channels: the tile kernel
 ]
 SMALL_3D = [
     ((37, 41, 29), 1, 1.0, 2), ((20, 33, 47), 2, 0.3, 2), ((17, 16, 16), 1, 0.0, 2), ((1, 40, 50), 1, 0.7, 2),
@@ -115,6 +118,14 @@ def test_records_match_oracle(shape, C, lam):
     assert np.array_equal(got, plain), "forward-with-records differs from plain forward"
     assert np.array_equal(got, ref)
     assert np.array_equal(rec, ref_rec), f"{int((rec != ref_rec).sum())} records differ"
+
+
+@pytest.mark.parametrize("shape,lam", [((3, 200000), 0.8), ((200000, 3), 1.0)])
+def test_2d_elongated(shape, lam):
+    """(3, 200000): the row passes along axis 0 have 6250 tiles, more than the
+    co-resident workgroups, so each workgroup runs several tiles per chunk;
+    (200000, 3): 12500 chunks of one tile along a 200000-row chain."""
+    check_case(synth.small_case(shape, C=1, seed=77, lam=lam, iterations=2))
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.5, 1.0])
