@@ -19,12 +19,13 @@ namespace dev {
 
 static_assert(kRowLanes == 64 && kRowTQ == kRowLanes - 2 * kRowK, "row tile: one wave, K halo cells per side");
 
-// Value of the lane to the left (lane - 1) / right (lane + 1); `fill` at the wave's ends.
-__device__ __forceinline__ float from_left(float v, float fill) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x138, 0xF, 0xF, false));
+// Value of the lane to the left (lane - 1) / right (lane + 1), 0 past the
+// wave's ends (lanes 0 and 63 are halo cells that never take part in a step).
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
-__device__ __forceinline__ float from_right(float v, float fill) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x130, 0xF, 0xF, false));
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
 // Edge cost through offset j from the registers of x (ix) and of its parent (iy).
@@ -103,23 +104,27 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
   };
 
   // Row j of an item is used by the cells within distance kk - j of the tile.
+  // Every lane loads the row (an unneeded one from a clamped, in-bounds
+  // address) and keeps the value only where it is needed: no branch.
   float nd[K + 1], nx[K + 1][NI];
+  auto fetch_row = [&](const Item& it, int j) {
+    const bool need = it.in && j <= it.kk && e <= it.kk - j;
+    const int x = need ? xof(it, j) : 0;
+    const float dv = dsrc0[x];
+    nd[j] = (need && (j >= 1 || it.c == 0)) ? dv : 0.0f;
+    if (USE_I) {
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const float iv = gImage[c * cstride + x];
+        nx[j][c] = need ? iv : 0.0f;
+      }
+    } else {
+      nx[j][0] = 0.0f;
+    }
+  };
   auto fetch = [&](const Item& it) {
 #pragma unroll
-    for (int j = 0; j <= K; ++j) {
-      const bool need = it.in && j <= it.kk && e <= it.kk - j;
-      nd[j] = 0.0f;
-#pragma unroll
-      for (int c = 0; c < NI; ++c) nx[j][c] = 0.0f;
-      if (need) {
-        const int x = xof(it, j);
-        if (j >= 1 || it.c == 0) nd[j] = dsrc0[x];
-        if (USE_I) {
-#pragma unroll
-          for (int c = 0; c < NI; ++c) nx[j][c] = gImage[c * cstride + x];
-        }
-      }
-    }
+    for (int j = 0; j <= K; ++j) fetch_row(it, j);
   };
 
   int chg = 0;  // an own cell was lowered (convergence mode)
@@ -177,51 +182,69 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
     float icur[NI];
 #pragma unroll
     for (int ch = 0; ch < NI; ++ch) icur[ch] = ix[0][ch];
-    unsigned long long* xout = xbuf + (size_t)(c & 1) * ntiles * TQ + (size_t)cur.tile * TQ;
-    // a fixed trip count with a uniform guard: the loop holds the convergent
-    // lane shifts, which keep it from being unrolled around an early exit
+    // The steps, branch-free: every lane computes, lanes outside the image keep
+    // +inf.  A lane of the shrinking cone (e <= kk - 1 - i) reads only lanes
+    // that were in the cone at the previous row, so values computed outside
+    // the cone are never used.  Full chunks run without a trip-count guard; the
+    // last one keeps a fixed trip count with a uniform guard (the loop holds
+    // the convergent lane shifts, which keep it from being unrolled around an
+    // early exit).
+    float res[K];
+    int rch[K];
+    auto step = [&](int i) {
+      // the previous row's neighbours, offsets j = 0 (q - 1), 1 (q), 2 (q + 1)
+      float dy[3], iy[3][NI];
+      dy[0] = from_left(dcur);
+      dy[1] = dcur;
+      dy[2] = from_right(dcur);
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (i < kk) {
-        // the previous row's neighbours, offsets j = 0 (q - 1), 1 (q), 2 (q + 1)
-        float dy[3], iy[3][NI];
-        dy[0] = from_left(dcur, __builtin_inff());
-        dy[1] = dcur;
-        dy[2] = from_right(dcur, __builtin_inff());
+      for (int ch = 0; ch < NI; ++ch) {
+        iy[0][ch] = from_left(icur[ch]);
+        iy[1][ch] = icur[ch];
+        iy[2][ch] = from_right(icur[ch]);
+      }
+      float best = dd[i + 1];
+      int choice = 0;
 #pragma unroll
-        for (int ch = 0; ch < NI; ++ch) {
-          iy[0][ch] = from_left(icur[ch], 0.0f);
-          iy[1][ch] = icur[ch];
-          iy[2][ch] = from_right(icur[ch], 0.0f);
+      for (int j = 0; j < 3; ++j) {
+        const float cand = dy[j] + row_edge<MODE, NI>(g, j, ix[i + 1], iy[j]);
+        if (REC) {
+          choice = cand < best ? 1 + j : choice;
+          best = cand < best ? cand : best;
+        } else {
+          best = fminf(best, cand);
         }
-        float dnew = dcur;
-        if (cur.in && e <= kk - 1 - i) {
-          float best = dd[i + 1];
-          int choice = 0;
+      }
+      res[i] = best;
+      rch[i] = choice;
+      dcur = cur.in ? best : __builtin_inff();
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            const float cand = dy[j] + row_edge<MODE, NI>(g, j, ix[i + 1], iy[j]);
-            if (REC) {
-              if (cand < best) {
-                best = cand;
-                choice = 1 + j;
-              }
-            } else {
-              best = fminf(best, cand);
-            }
-          }
-          dnew = best;
-          if (e == 0) {
-            chg |= best < dd[i + 1];
-            const int x = xof(cur, i + 1);
-            gD[x] = best;
-            if (REC && g.rec) gRec[x] = (uint8_t)choice;
-            if (i == kk - 1) st64_relaxed(xout + own, ((unsigned long long)epoch_out << 32) | __float_as_uint(best));
-          }
+      for (int ch = 0; ch < NI; ++ch) icur[ch] = ix[i + 1][ch];
+    };
+    if (kk == K) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) step(i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if (i < kk) step(i);
+    }
+    // The tile's own cells: the exchange word of the chunk's last row first
+    // (the neighbours wait for it), then the rows.
+    if (cur.in && e == 0) {
+      unsigned long long* xout = xbuf + (size_t)(c & 1) * ntiles * TQ + (size_t)cur.tile * TQ;
+      float last = res[0];
+#pragma unroll
+      for (int i = 1; i < K; ++i) last = i < kk ? res[i] : last;
+      st64_relaxed(xout + own, ((unsigned long long)epoch_out << 32) | __float_as_uint(last));
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if (i < kk) {
+          const int x = xof(cur, i + 1);
+          chg |= res[i] < dd[i + 1];
+          gD[x] = res[i];
+          if (REC && g.rec) gRec[x] = (uint8_t)rch[i];
         }
-        dcur = dnew;
-#pragma unroll
-        for (int ch = 0; ch < NI; ++ch) icur[ch] = ix[i + 1][ch];
       }
     }
     cur = nxt;
