@@ -65,7 +65,8 @@ __device__ __forceinline__ bool run_pass_rt(const PassDesc* gp, unsigned long lo
   return run_pass_mode<NDIM, TP, TQ, K, false, kModeGeneral, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
 }
 
-template <int K3, int K2, bool REC>
+// CT: tile side of the thread-per-cell pass for 3D instances (0: the tile pass).
+template <int K3, int K2, bool REC, int CT>
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                            const PassDesc* __restrict__ passes, unsigned char* ws,
                                                            unsigned long long limit) {
@@ -89,8 +90,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst*
     const PassDesc* gp = passes + in.pass0 + p;
     bool ok;
     if (in.ndim == 3) {
-      if constexpr (K3 == kCellK)
-        ok = run_pass_cell_rt<REC>(gp, xbuf, words, cls, in.mode, limit, carve_cell_lds(lds), wg, in.nwg);
+      if constexpr (CT != 0)
+        ok = run_pass_cell_rt<REC, CT, K3>(gp, xbuf, words, cls, in.mode, limit, carve_cell_lds(lds), wg, in.nwg);
       else
         ok = run_pass_rt<3, kTP3, kTQ3, K3, REC>(gp, xbuf, words, cls, in.mode, limit, lds, wg, in.nwg);
     } else {
@@ -125,16 +126,27 @@ __global__ __launch_bounds__(256) void batched_classify_kernel(const BatchInst* 
 
 using BatchedKernel = void (*)(const BatchInst*, int, const PassDesc*, unsigned char*, unsigned long long);
 
-BatchedKernel pick(int kclass, bool rec) {
-  if (kclass == 0) return rec ? batched_kernel<kBatchK3[0], kBatchK2[0], true> : batched_kernel<kBatchK3[0], kBatchK2[0], false>;
-  return rec ? batched_kernel<kBatchK3[1], kBatchK2[1], true> : batched_kernel<kBatchK3[1], kBatchK2[1], false>;
+static_assert(kBatchTile3[0] == kCellTP && kBatchK3[0] == kCellK && kBatchTile3[2] == kCellWideTP &&
+                  kBatchK3[2] == kCellWideK,
+              "batched classes 0 and 2 run the thread-per-cell pass geometries");
+
+template <int C>
+BatchedKernel pick_class(bool rec) {
+  constexpr int CT = C == 1 ? 0 : kBatchTile3[C];
+  return rec ? batched_kernel<kBatchK3[C], kBatchK2[C], true, CT> : batched_kernel<kBatchK3[C], kBatchK2[C], false, CT>;
 }
 
-template <int K3, int K2>
+BatchedKernel pick(int kclass, bool rec) {
+  if (kclass == 0) return pick_class<0>(rec);
+  if (kclass == 2) return pick_class<2>(rec);
+  return pick_class<1>(rec);
+}
+
+template <int K3, int K2, bool CELL>
 size_t lds_for(int C, bool has2d, bool has3d) {
   size_t b = 0;
   if (has3d) {
-    if (K3 == kCellK) {
+    if (CELL) {
       b = max(b, kCellLdsBytes);
     } else {
       b = max(b, Layout<3, kTP3, kTQ3, K3, true>::bytes(C));
@@ -151,8 +163,9 @@ size_t lds_for(int C, bool has2d, bool has3d) {
 }  // namespace
 
 size_t batched_lds_bytes(int kclass, int C, bool has2d, bool has3d) {
-  return kclass == 0 ? lds_for<kBatchK3[0], kBatchK2[0]>(C, has2d, has3d)
-                     : lds_for<kBatchK3[1], kBatchK2[1]>(C, has2d, has3d);
+  if (kclass == 0) return lds_for<kBatchK3[0], kBatchK2[0], true>(C, has2d, has3d);
+  if (kclass == 2) return lds_for<kBatchK3[2], kBatchK2[2], true>(C, has2d, has3d);
+  return lds_for<kBatchK3[1], kBatchK2[1], false>(C, has2d, has3d);
 }
 
 int batched_capacity(int kclass, bool rec, size_t lds) {

@@ -59,6 +59,21 @@ int max_tiles_of(const std::vector<PassDesc>& ps) {
   return m;
 }
 
+// Exchange words one parity slot of an instance needs: tiles x tile cells, for
+// the forward passes' tiles and for the reverse passes' (16 x 16 in 3D, 256
+// in 2D), which reuse the instance's exchange area.
+size_t max_cells_of(const std::vector<PassDesc>& ps) {
+  size_t m = 1;
+  for (const PassDesc& d : ps) {
+    const size_t fwd = (size_t)d.ntp * d.ntq * d.TP * d.TQ;
+    const size_t bwd = d.TP == 1 ? (size_t)((d.Nq + kTQ2 - 1) / kTQ2) * kTQ2
+                                 : (size_t)((d.Np + kTP3 - 1) / kTP3) * ((d.Nq + kTQ3 - 1) / kTQ3) * kTP3 * kTQ3;
+    m = fwd > m ? fwd : m;
+    m = bwd > m ? bwd : m;
+  }
+  return m;
+}
+
 int validate_instance(const ggdt_instance& in, Problem* pr) {
   if (!in.image || !in.softmask || !in.out) return GGDT_ERR_NULL_PTR;
   int rc = make_problem(in.ndim, in.dims, in.C, pr);
@@ -107,7 +122,15 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     any_cls = true;  // the classification decides every instance's edge-cost mode
   }
   int kclass = maxC <= kBatchMaxC[0] ? 0 : 1;
-  if (tuning && tuning->chunk > 0) {
+  const bool wide = tuning && (tuning->tile_p == kBatchTile3[2] || tuning->tile_q == kBatchTile3[2]);
+  if (tuning && (tuning->tile_p > 0 || tuning->tile_q > 0) && !wide &&
+      !(tuning->tile_p == kBatchTile3[0] || tuning->tile_q == kBatchTile3[0]))
+    return GGDT_ERR_BAD_PARAM;
+  if (wide) {
+    // 24 x 24 volume tiles with K = 4: single-channel batches only
+    if (tuning->chunk > 0 && tuning->chunk != kBatchK3[2]) return GGDT_ERR_BAD_PARAM;
+    kclass = 2;
+  } else if (tuning && tuning->chunk > 0) {
     if (tuning->chunk == kBatchK3[1] || tuning->chunk == kBatchK2[1]) kclass = 1;
     else if (tuning->chunk != kBatchK3[0] && tuning->chunk != kBatchK2[0]) return GGDT_ERR_BAD_PARAM;
   }
@@ -138,6 +161,11 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
       rc = build_pass(prs[i], in.image, in.softmask, in.spacing, in.v, in.lambda, in.out, in.records, p, base, &d);
       if (rc) return rc;
       d.K = in.ndim == 3 ? kBatchK3[kclass] : kBatchK2[kclass];
+      if (in.ndim == 3) {
+        d.TP = d.TQ = kBatchTile3[kclass];
+        d.ntp = (d.Np + d.TP - 1) / d.TP;
+        d.ntq = (d.Nq + d.TQ - 1) / d.TQ;
+      }
       d.nchunk = (d.Na - 1 + d.K - 1) / d.K;
       base += (unsigned)d.nchunk + 1u;
       passes[i].push_back(d);
@@ -190,8 +218,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     bi.cls_off = (long long)(cls_off + 4 * (size_t)i);
     bi.image = in.image;
     bi.nimg = (long long)prs[i].C * prs[i].N;
-    const int TPQ = in.ndim == 3 ? kTP3 * kTQ3 : kTQ2;
-    off = align_up(off + (size_t)2 * max_tiles_of(passes[i]) * TPQ * 8);
+    off = align_up(off + (size_t)2 * max_cells_of(passes[i]) * 8);
     wg0 += w[i];
     for (const PassDesc& d : passes[i]) flat.push_back(d);
     plan->h_insts.push_back(bi);

@@ -129,11 +129,15 @@ constexpr int kTP3 = 16, kTQ3 = 16, kTQ2 = 256;
 // kRowTQ = 64 - 2 kRowK owned cells per tile, images of up to kRowMaxC channels.
 constexpr int kRowLanes = 64, kRowK = 16, kRowTQ = kRowLanes - 2 * kRowK, kRowMaxC = 3;
 
-// Chunk lengths of the two batched kernel classes: class 0 for single-channel
-// batches, class 1 for up to 4 channels.
-constexpr int kBatchK3[2] = {8, 4};
-constexpr int kBatchK2[2] = {32, 16};
-constexpr int kBatchMaxC[2] = {1, 4};
+// Batched kernel classes: 0 for single-channel batches (3D: thread-per-cell
+// pass on 16 x 16 tiles, K = 8); 1 for up to 4 channels (tile passes, K = 4 /
+// 16); 2 single-channel, chosen by tuning (3D: thread-per-cell pass on 24 x 24
+// tiles, K = 4, less halo arithmetic for twice the exchanges).  Chunk lengths
+// (3D / 2D), 3D tile side, channel limit:
+constexpr int kBatchK3[3] = {8, 4, 4};
+constexpr int kBatchK2[3] = {32, 16, 32};
+constexpr int kBatchTile3[3] = {16, 16, 24};
+constexpr int kBatchMaxC[3] = {1, 4, 1};
 
 size_t batched_lds_bytes(int kclass, int C, bool has2d, bool has3d);
 int batched_capacity(int kclass, bool rec, size_t lds);

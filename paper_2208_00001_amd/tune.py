@@ -1,9 +1,9 @@
 """Autotuner for the batched launch.
 
 Times candidate schedules of a batch (chunk length K, i.e. the halo depth and
-the number of scan steps between neighbour exchanges, and the number of
-co-resident workgroups planned per compute unit) with HIP-graph replays and
-keeps the fastest.  Results are cached in a JSON file keyed by the batch's shape
+the number of scan steps between neighbour exchanges; the 3D tile side, 16 or
+24 for single-channel volumes; and the number of co-resident workgroups
+planned per compute unit) with HIP-graph replays and keeps the fastest.  Results are cached in a JSON file keyed by the batch's shape
 signature (GGDT_TUNE_CACHE, default ~/.cache/ggdt_tune.json).
 """
 from __future__ import annotations
@@ -20,6 +20,8 @@ CANDIDATES = (
     {"chunk": 4, "wg_per_cu": 1},
     {"chunk": 4, "wg_per_cu": 2},
     {"chunk": 4, "wg_per_cu": 0},
+    {"chunk": 4, "tile_p": 24, "wg_per_cu": 1},
+    {"chunk": 4, "tile_p": 24, "wg_per_cu": 0},
 )
 
 

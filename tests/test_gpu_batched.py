@@ -38,11 +38,18 @@ def to_instances(cases, records=False):
                  iterations=c["iterations"], records=records) for c in cases]
 
 
+# default class (16 x 16 volume tiles, K = 8), the multi-channel class forced
+# (K = 4 tile passes), and 24 x 24 volume tiles with K = 4
+TUNINGS = [None, {"chunk": 4}, {"chunk": 4, "tile_p": 24}]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=["default", "k4", "wide"])
 @pytest.mark.parametrize("records", [False, True])
-def test_small_ragged_batch_matches_oracle(records):
+def test_small_ragged_batch_matches_oracle(records, tuning):
     from paper_2208_00001_amd.batched import BatchedPlan
     cases = small_batch()
-    plan = BatchedPlan(to_instances(cases, records))
+    plan = BatchedPlan(to_instances(cases, records), tuning)
+    print("plan", tuning, plan.info(), flush=True)
     plan.run()
     assert plan.status() == 0
     for c, d in zip(cases, plan.inst):
@@ -80,11 +87,12 @@ def _sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def test_config4_batch_equals_plain_launches_and_oracle():
+@pytest.mark.parametrize("tuning", [None, {"chunk": 4, "tile_p": 24}], ids=["default", "wide"])
+def test_config4_batch_equals_plain_launches_and_oracle(tuning):
     from paper_2208_00001_amd import binding as B
     from paper_2208_00001_amd.batched import BatchedPlan
     cases = synth.config4()
-    plan = BatchedPlan(to_instances(cases))
+    plan = BatchedPlan(to_instances(cases), tuning)
     plan.capture()
     plan.replay()
     torch.cuda.synchronize()
@@ -102,16 +110,21 @@ def test_config4_batch_equals_plain_launches_and_oracle():
     plan.close()
 
 
-@pytest.mark.parametrize("kind", ["mixed", "volumes"])
+@pytest.mark.parametrize("kind", ["mixed", "volumes", "volumes-wide"])
 def test_small_ragged_batch_backward(kind):
     """Batched forward with records + batched backward for every instance, vs the
     single-instance launches and the oracle's FP32 reverse pass (bitwise).
     'mixed': 2D and 3D, 1-3 channels (tile reverse passes); 'volumes':
     single-channel volumes of different shapes only (thread-per-cell reverse
-    pass, with more workgroups than some passes have tiles)."""
+    pass, with more workgroups than some passes have tiles); 'volumes-wide':
+    the same after a forward on 24 x 24 tiles (the reverse pass's 16 x 16
+    tiles then need more exchange words than the forward's)."""
     from paper_2208_00001_amd import binding as B
     from paper_2208_00001_amd.batched import BatchedPlan
-    if kind == "mixed":
+    if kind == "volumes-wide":
+        # 65-cell planes: 9 tiles of 24 x 24 (5184 cells) against 25 of 16 x 16 (6400)
+        specs = [((65, 65, 40), 1, 0.7, 2), ((19, 65, 65), 1, 1.0, 1), ((50, 26, 49), 1, 0.3, 2)]
+    elif kind == "mixed":
         specs = [((29, 23, 31), 1, 0.7, 2), ((200, 137), 2, 0.5, 2), ((17, 40, 22), 3, 0.4, 1), ((90, 301), 1, 1.0, 2),
                  ((12, 13, 70), 1, 0.0, 2)]  # channel counts within the batched reverse pass's LDS (2D <= 2, 3D <= 3)
     else:
@@ -125,7 +138,7 @@ def test_small_ragged_batch_backward(kind):
     inst = to_instances(cases, True)
     for d, c in zip(inst, cases):
         d["grad_out"] = to_dev(c["weight"])
-    plan = BatchedPlan(inst)
+    plan = BatchedPlan(inst, {"chunk": 4, "tile_p": 24} if kind == "volumes-wide" else None)
     print("plan", plan.info(), flush=True)
     plan.run()
     grads = plan.backward()
