@@ -237,9 +237,12 @@ typedef struct ggdt_plan ggdt_plan;
  * until ggdt_plan_destroy.  Errors are those of the plain entries, for the first
  * offending instance. */
 typedef struct ggdt_tuning {
-  int tile_p;      /* 3D plane tile rows (0 = default) */
-  int tile_q;      /* 3D plane tile width / 2D row tile width (0 = default) */
-  int chunk;       /* scan steps between inter-workgroup syncs (0 = default) */
+  int tile_p;      /* 3D plane tile side: 0 or 16 (default), or 24 (single-channel batches only; 24 x 24
+                      tiles with chunk 4: less halo arithmetic for more exchanges); other values
+                      GGDT_ERR_BAD_PARAM */
+  int tile_q;      /* same as tile_p (either selects the side) */
+  int chunk;       /* scan steps between inter-workgroup syncs: 0 (default), 8 or 32 (single-channel
+                      kernels), 4 or 16 (kernels for up to 4 channels); 0 or 4 with tile side 24 */
   int wg_per_cu;   /* resident workgroups per compute unit to plan for (0 = default) */
 } ggdt_tuning;
 

@@ -136,3 +136,27 @@ def test_composed_validation_codes(lib):
     assert lib.ggdt2d_signed(None, ctypes.c_void_p(FAKE + (1 << 30)), sp, 1e10, 1.0, 2,
                              ctypes.c_void_p(FAKE + (2 << 30)), 1, 8, 8, ctypes.c_void_p(FAKE + (3 << 30)), 1 << 30,
                              None) == -1
+
+
+def test_batched_tuning_validation(lib):
+    """Tile sides other than 16 / 24, or a chunk the chosen class does not run, are
+    rejected before the device is touched; 24 is single-channel only."""
+    from paper_2208_00001_amd.binding import GGDTInstance, GGDTTuning
+    inst = GGDTInstance()
+    inst.ndim, inst.C = 3, 1
+    inst.dims[0], inst.dims[1], inst.dims[2] = 8, 8, 8
+    inst.image, inst.softmask, inst.out = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
+    inst.spacing[0] = inst.spacing[1] = inst.spacing[2] = 1.0
+    inst.v, inst.lam, inst.iterations = 1e10, 0.5, 2
+    plan, wsb = ctypes.c_void_p(), ctypes.c_size_t()
+
+    def call(tp, chunk, C=1):
+        inst.C = C
+        t = GGDTTuning(tp, 0, chunk, 0)
+        return lib.ggdt_batched_plan(ctypes.byref(inst), 1, ctypes.byref(t), ctypes.byref(plan), ctypes.byref(wsb))
+
+    assert call(20, 0) == -3
+    assert call(24, 8) == -3
+    assert call(24, 16) == -3
+    assert call(16, 5) == -3
+    assert call(24, 4, C=2) == -8  # wide tiles: single-channel batches only
