@@ -279,7 +279,9 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
             d.a_in = prev_gm ? in.grad_softmask : nullptr;
             d.a_in_off = prev_gm ? -1 : scratch_off[i];
           }
-          PassDesc geo;
+          PassDesc geo{};
+          geo.TP = d.TP;
+          geo.TQ = d.TQ;
           geo.Na = d.Na;
           geo.ntp = d.ntp;
           geo.ntq = d.ntq;
