@@ -104,27 +104,33 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
   };
 
   // Row j of an item is used by the cells within distance kk - j of the tile.
-  // Every lane loads the row (an unneeded one from a clamped, in-bounds
-  // address) and keeps the value only where it is needed: no branch.
+  // Every lane loads every row (an unneeded one from a clamped, in-bounds
+  // address) and keeps the value only where it is needed: no branch.  Row j
+  // lies sign * sa elements after row j - 1.
   float nd[K + 1], nx[K + 1][NI];
-  auto fetch_row = [&](const Item& it, int j) {
-    const bool need = it.in && j <= it.kk && e <= it.kk - j;
-    const int x = need ? xof(it, j) : 0;
-    const float dv = dsrc0[x];
-    nd[j] = (need && (j >= 1 || it.c == 0)) ? dv : 0.0f;
-    if (USE_I) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const float iv = gImage[c * cstride + x];
-        nx[j][c] = need ? iv : 0.0f;
-      }
-    } else {
-      nx[j][0] = 0.0f;
-    }
-  };
   auto fetch = [&](const Item& it) {
+    const int x0 = xof(it, 0);
+    const int step = g.sign * g.sa;
+    const int last = it.in ? it.kk - e : -1;  // the lane needs rows 0 .. last
 #pragma unroll
-    for (int j = 0; j <= K; ++j) fetch_row(it, j);
+    for (int j = 0; j <= K; ++j) {
+      const bool need = j <= last;
+      int x = need ? x0 + j * step : 0;
+      // opaque to the optimiser, which would otherwise turn the clamped load
+      // and the select back into a branch per row
+      __asm__ volatile("" : "+v"(x));
+      const float dv = dsrc0[x];
+      nd[j] = (need && (j >= 1 || it.c == 0)) ? dv : 0.0f;
+      if (USE_I) {
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          const float iv = gImage[c * cstride + x];
+          nx[j][c] = need ? iv : 0.0f;
+        }
+      } else {
+        nx[j][0] = 0.0f;
+      }
+    }
   };
 
   int chg = 0;  // an own cell was lowered (convergence mode)
