@@ -16,7 +16,7 @@
  *     w(x,y) = sqrt((1 - lambda) * |x - y|_s^2 + lambda * sum_c (I_c(x) - I_c(y))^2)
  *     one pass: D(x) <- min(D(x), min over y in the previous row/plane of D(y) + w(x,y))
  *
- * Readings of points the paper leaves open (each listed in the design doc):
+ * Readings of points the paper leaves open:
  *  - only the 3 (2D) / 9 (3D) neighbours in the previous row/plane are used;
  *    the current value D(x) takes part in the min ("keep");
  *  - passes per iteration: for axis 0..ndim-1: ascending, then descending;
