@@ -160,3 +160,19 @@ def test_batched_tuning_validation(lib):
     assert call(24, 16) == -3
     assert call(16, 5) == -3
     assert call(24, 4, C=2) == -8  # wide tiles: single-channel batches only
+
+
+def test_workspace_covers_2d_row_tiles(lib):
+    """The 2D row kernel (one wave per 32-cell tile) exchanges two parity slots of
+    one 8-byte word per tile cell; the workspace the library asks for must hold
+    them (after its 256-byte header) for the rows of either pass axis."""
+    import random
+    rnd = random.Random(7)
+    shapes = [(1, 1), (1, 33), (256, 256), (255, 257), (31, 1025), (2048, 2048), (3, 200000), (200000, 3)]
+    shapes += [(rnd.randint(1, 5000), rnd.randint(1, 5000)) for _ in range(200)]
+    for H, W in shapes:
+        for C in (1, 2, 3):
+            ws = lib.ggdt_workspace_bytes(2, (ctypes.c_int * 2)(H, W), C)
+            for nq in (W, H):  # row length of the axis-0 and axis-1 passes
+                need = 256 + 2 * (-(-nq // 32)) * 32 * 8
+                assert ws >= need, (H, W, C, ws, need)
