@@ -109,7 +109,7 @@ def test_general_root_over_wide_magnitudes(shape, C, lam, spacing):
 
 
 @pytest.mark.parametrize("shape,C,lam", [((40, 37, 33), 1, 1.0), ((19, 50, 21), 2, 0.6), ((300, 270), 1, 0.0),
-                                         ((270, 300), 3, 0.4)])
+                                         ((270, 300), 3, 0.4), ((33, 65), 2, 1.0)])
 def test_records_match_oracle(shape, C, lam):
     c = synth.small_case(shape, C=C, seed=8, lam=lam, iterations=2, soft=True, v=5.0)
     got, rec = gpu_forward(c, records=True)

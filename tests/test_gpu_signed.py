@@ -49,6 +49,7 @@ CASES = [
     ((17, 20, 21), 2, 0.4, 1, False),
     ((1, 33, 40), 1, 0.5, 2, True),
     ((12, 14), 1, 0.5, 0, True),
+    ((40, 50), 4, 0.6, 2, False),  # four channels: the 2D tile kernel
 ]
 
 
