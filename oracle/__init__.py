@@ -305,3 +305,49 @@ def backward(image, records, grad_out, spacing, v, lam, iterations, precision="f
                                        ctypes.c_double(lam), int(iterations), _p(rec), _p(go), _p(gi), _p(gm))
     _check(rc, "ref_ggdt_backward")
     return gi, gm
+
+
+class PerturbedF64:
+    """Exact incremental re-evaluation of the FP64 schedule for single-voxel
+    changes of the input (a checker for central differences).
+
+    Holds the base run's state after every pass (``ref_ggdt_f64_trajectory``);
+    ``run(which, index, delta)`` returns (D, records_unchanged) of the FP64
+    schedule on the input with M[index] (which = "M") or I[channel][index]
+    (which = "I") increased by delta, equal bit for bit to ``ggdt(...,
+    "f64", records=True)`` on that input.  ``run`` may be called from several
+    threads at once (the library call releases the GIL)."""
+
+    def __init__(self, image, mask, spacing, v, lam, iterations):
+        lib = _load()
+        image, spatial = _split(image, mask)
+        self.img, self.m, self.sp = _f64(image), _f64(mask), _f64(spacing)
+        self.spatial, self.C = spatial, image.shape[0]
+        self.v, self.lam, self.iterations = float(v), float(lam), int(iterations)
+        n = int(np.prod(spatial))
+        npass = self.iterations * 2 * len(spatial)
+        self.traj = np.empty((npass + 1,) + spatial, dtype=np.float64)
+        self.records = np.empty((npass,) + spatial, dtype=np.uint8)
+        rc = lib.ref_ggdt_f64_trajectory(len(spatial), _dims(spatial), self.C, _p(self.img), _p(self.m),
+                                         _p(self.sp), ctypes.c_double(self.v), ctypes.c_double(self.lam),
+                                         self.iterations, _p(self.traj), _p(self.records))
+        _check(rc, "ref_ggdt_f64_trajectory")
+        self.n = n
+
+    @property
+    def base(self):
+        """The base run's final D."""
+        return self.traj[-1]
+
+    def run(self, which, index, delta, channel=0):
+        lib = _load()
+        flat = int(np.ravel_multi_index(tuple(index), self.spatial))
+        out = np.empty(self.spatial, dtype=np.float64)
+        same = ctypes.c_int(0)
+        rc = lib.ref_ggdt_f64_perturbed(len(self.spatial), _dims(self.spatial), self.C, _p(self.img), _p(self.m),
+                                        _p(self.sp), ctypes.c_double(self.v), ctypes.c_double(self.lam),
+                                        self.iterations, _p(self.traj), _p(self.records),
+                                        0 if which == "M" else 1, int(channel), ctypes.c_long(flat),
+                                        ctypes.c_double(delta), _p(out), ctypes.byref(same))
+        _check(rc, "ref_ggdt_f64_perturbed")
+        return out, bool(same.value)

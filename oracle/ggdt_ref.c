@@ -1041,3 +1041,208 @@ int ref_pass_bruteforce_f64(int ndim, const int* dims, int C, const double* imag
 #define CAST_F64(x) ((double)(x))
 DEFINE_BACKWARD(ref_ggdt_backward_f32, float, edge_w_f32, CAST_F32)
 DEFINE_BACKWARD(ref_ggdt_backward_f64, double, edge_w_f64, CAST_F64)
+
+/* ------------------------------------- incremental FP64 re-evaluation (checker)
+ * The central-difference check of the gradient evaluates the FP64 schedule on
+ * many inputs that differ from one base input at a single voxel (of M, or of
+ * one image channel).  In a pass, a voxel's new value and record depend only on
+ * its own value before the pass, its image values, and its parents' values
+ * after their own update in that pass together with their image values.  So a
+ * voxel none of whose inputs differ from the base run gets the base run's value
+ * and record.  ref_ggdt_f64_trajectory stores the base run's state after every
+ * pass; ref_ggdt_f64_perturbed recomputes, pass by pass and plane by plane in
+ * scan order, only the voxels whose inputs may differ (a bounding box that
+ * holds every one of them), with the arithmetic of pass_f64, and takes every
+ * other voxel from the stored state.  Its output equals ref_ggdt_f64 on the
+ * perturbed input bit for bit (tested against it); it is a faster way to get
+ * the same numbers, not a different computation. */
+
+/* State of the base run: traj[p * n ..] after p passes (traj[0] = v * M),
+ * p = 0 .. npass; records as ref_ggdt_f64. */
+int ref_ggdt_f64_trajectory(int ndim, const int* dims, int C, const double* image, const double* mask,
+                            const double* spacing, double v, double lam, int iterations, double* traj,
+                            uint8_t* records) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, traj, &g);
+  if (rc) return rc;
+  if (!records) return REF_EINVAL;
+  for (long i = 0; i < g.n; ++i) traj[i] = v * mask[i];
+  int p = 0;
+  for (int it = 0; it < iterations; ++it)
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s, ++p) {
+        memcpy(traj + (long)(p + 1) * g.n, traj + (long)p * g.n, sizeof(double) * (size_t)g.n);
+        pass_f64(&g, C, image, spacing, lam, a, s == 0 ? +1 : -1, traj + (long)(p + 1) * g.n,
+                 records + (long)p * g.n);
+      }
+  return REF_OK;
+}
+
+typedef struct {
+  int lo[3], hi[3];
+  int empty;
+} box_t;
+
+static void box_add(box_t* b, int ndim, const int* c) {
+  for (int i = 0; i < ndim; ++i) {
+    if (b->empty || c[i] < b->lo[i]) b->lo[i] = c[i];
+    if (b->empty || c[i] > b->hi[i]) b->hi[i] = c[i];
+  }
+  b->empty = 0;
+}
+
+/* Union of box u with box s grown by r on every axis (clipped to the grid). */
+static void box_union_grown(box_t* u, const box_t* s, int r, const grid_t* g) {
+  if (s->empty) return;
+  int lo[3], hi[3];
+  for (int i = 0; i < g->ndim; ++i) {
+    lo[i] = s->lo[i] - r < 0 ? 0 : s->lo[i] - r;
+    hi[i] = s->hi[i] + r > g->dims[i] - 1 ? g->dims[i] - 1 : s->hi[i] + r;
+  }
+  box_add(u, g->ndim, lo);
+  box_add(u, g->ndim, hi);
+}
+
+static int same_bits(double x, double y) { return memcmp(&x, &y, sizeof x) == 0; }
+
+/* The FP64 schedule on the base input with one value changed: which = 0 sets
+ * M(index) to mask[index] + delta, which = 1 sets I_channel(index) to
+ * image[channel * n + index] + delta.  traj and records come from
+ * ref_ggdt_f64_trajectory on the base input.  out receives the final D;
+ * *same_records is 1 when every record equals the base run's.  Scratch: two
+ * arrays of n values, one image copy. */
+int ref_ggdt_f64_perturbed(int ndim, const int* dims, int C, const double* image, const double* mask,
+                           const double* spacing, double v, double lam, int iterations, const double* traj,
+                           const uint8_t* records, int which, int channel, long index, double delta, double* out,
+                           int* same_records) {
+  grid_t g;
+  int rc = check_common(ndim, dims, C, image, mask, spacing, iterations, out, &g);
+  if (rc) return rc;
+  if (!traj || !records || !same_records || index < 0 || index >= g.n || (which != 0 && which != 1) ||
+      (which == 1 && (channel < 0 || channel >= C)))
+    return REF_EINVAL;
+  const long n = g.n;
+  const int npass = iterations * 2 * ndim;
+  double* P = (double*)malloc(sizeof(double) * (size_t)n);
+  uint8_t* chg = (uint8_t*)calloc((size_t)n, 1);
+  double* img = (double*)malloc(sizeof(double) * (size_t)n * (size_t)C);
+  if (!P || !chg || !img) {
+    free(P);
+    free(chg);
+    free(img);
+    return REF_ENOMEM;
+  }
+  memcpy(img, image, sizeof(double) * (size_t)n * (size_t)C);
+  int pc[3] = {0, 0, 0};
+  unflatten(&g, index, pc);
+  if (which == 0) {
+    const double d0 = v * (mask[index] + delta);
+    if (!same_bits(d0, traj[index])) {
+      chg[index] = 1;
+      P[index] = d0;
+    }
+  } else {
+    img[(long)channel * n + index] = image[(long)channel * n + index] + delta;
+  }
+  const int img_pert = which == 1 && !same_bits(img[(long)channel * n + index], image[(long)channel * n + index]);
+  int same = 1;
+  int p = 0;
+  for (int it = 0; it < iterations; ++it)
+    for (int a = 0; a < ndim; ++a)
+      for (int s = 0; s < 2; ++s, ++p) {
+        const int sign = s == 0 ? +1 : -1;
+        const double* before = traj + (long)p * n;
+        const double* after = traj + (long)(p + 1) * n;
+        const uint8_t* rec0 = records + (long)p * n;
+        int delta_[9][3];
+        const int nd = pass_offsets(ndim, a, delta_);
+        double A[9];
+        for (int j = 0; j < nd; ++j) {
+          int dx[3] = {delta_[j][0], delta_[j][1], delta_[j][2]};
+          dx[a] = 1;
+          A[j] = (1.0 - lam) * spatial_sq(ndim, spacing, dx);
+        }
+        /* voxels whose value before the pass differs, and the changed image voxel */
+        box_t b0 = {{0, 0, 0}, {0, 0, 0}, 1};
+        for (long i = 0; i < n; ++i)
+          if (chg[i]) {
+            int c[3];
+            unflatten(&g, i, c);
+            box_add(&b0, ndim, c);
+          }
+        if (img_pert) box_add(&b0, ndim, pc);
+        if (b0.empty) continue; /* nothing differs: the base state after this pass holds */
+        const int Na = g.dims[a];
+        const int k0 = sign > 0 ? 0 : Na - 1;
+        /* changed voxels of the previous plane (the first plane is not modified) */
+        box_t prev = {{0, 0, 0}, {0, 0, 0}, 1};
+        if (b0.lo[a] <= k0 && k0 <= b0.hi[a]) {
+          prev = b0;
+          prev.lo[a] = prev.hi[a] = k0;
+        }
+        for (int t = 1; t < Na; ++t) {
+          const int k = sign > 0 ? t : Na - 1 - t;
+          box_t r = {{0, 0, 0}, {0, 0, 0}, 1};
+          if (b0.lo[a] <= k && k <= b0.hi[a]) box_union_grown(&r, &b0, 0, &g);
+          box_union_grown(&r, &prev, 1, &g);
+          if (img_pert && pc[a] == k - sign) {
+            box_t e = {{pc[0], pc[1], pc[2]}, {pc[0], pc[1], pc[2]}, 0};
+            box_union_grown(&r, &e, 1, &g);
+          }
+          box_t next = {{0, 0, 0}, {0, 0, 0}, 1};
+          if (!r.empty) {
+            r.lo[a] = r.hi[a] = k;
+            int xc[3] = {r.lo[0], r.lo[1], r.lo[2]};
+            for (;;) {
+              const long x = flatten(&g, xc);
+              int need = chg[x] || (img_pert && x == index);
+              long ys[9];
+              int ok[9];
+              for (int j = 0; j < nd; ++j) {
+                int yc[3];
+                for (int b = 0; b < ndim; ++b) yc[b] = xc[b] + delta_[j][b];
+                yc[a] = k - sign;
+                ok[j] = in_grid(&g, yc);
+                ys[j] = ok[j] ? flatten(&g, yc) : -1;
+                if (ok[j] && (chg[ys[j]] || (img_pert && ys[j] == index))) need = 1;
+              }
+              if (need) {
+                double best = chg[x] ? P[x] : before[x];
+                uint8_t choice = 0;
+                for (int j = 0; j < nd; ++j) {
+                  if (!ok[j]) continue;
+                  const long y = ys[j];
+                  const double dy = chg[y] ? P[y] : after[y];
+                  const double w = edge_w_f64(img, n, C, x, y, lam, A[j]);
+                  const double cand = dy + w;
+                  if (cand < best) {
+                    best = cand;
+                    choice = (uint8_t)(1 + j);
+                  }
+                }
+                if (choice != rec0[x]) same = 0;
+                chg[x] = !same_bits(best, after[x]);
+                P[x] = best;
+                if (chg[x]) box_add(&next, ndim, xc);
+              }
+              /* next voxel of the box, row-major over the non-scan axes */
+              int b = ndim - 1;
+              for (; b >= 0; --b) {
+                if (b == a) continue;
+                if (++xc[b] <= r.hi[b]) break;
+                xc[b] = r.lo[b];
+              }
+              if (b < 0) break;
+            }
+          }
+          prev = next;
+        }
+      }
+  const double* fin = traj + (long)npass * n;
+  for (long i = 0; i < n; ++i) out[i] = chg[i] ? P[i] : fin[i];
+  *same_records = same;
+  free(P);
+  free(chg);
+  free(img);
+  return REF_OK;
+}

@@ -65,6 +65,24 @@ def test_hand_worked_examples(case):
         np.testing.assert_allclose(full, exp, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_hand_worked_examples_f32(case):
+    """The FP32 schedule on the same hand-worked cases: every snapshot within the
+    FP32 rounding bound of a path sum (each edge cost within 3 ulp-units of its
+    exact value, one rounding per addition), (K + 5) 2^-24 relative with K the
+    number of plane steps the passes so far contain."""
+    image = np.array(case["image"], dtype=np.float32)
+    mask = np.array(case["mask"], dtype=np.float32)
+    nd = mask.ndim
+    for npass, expected in case["after_pass"].items():
+        exp = np.vectorize(_eval)(np.array(expected, dtype=object)).astype(np.float64)
+        got = _run_passes(image, mask, case["spacing"], case["v"], case["lam"], int(npass), "f32")
+        sched = oracle.pass_schedule(nd, (int(npass) + 2 * nd - 1) // (2 * nd))[:int(npass)]
+        K = sum(mask.shape[a] - 1 for a, _ in sched)
+        bound = (K + 5) * 2.0 ** -24 * np.abs(exp)
+        assert np.all(np.abs(got.astype(np.float64) - exp) <= bound), (npass, got, exp)
+
+
 # ---------------------------------------------------------- lambda = 0 closed form
 
 @pytest.mark.parametrize("shape,spacing,seed", [
@@ -363,6 +381,69 @@ def test_backward_f32_close_to_f64():
     np.testing.assert_allclose(gM32, gM64, rtol=1e-4, atol=1e-4)
     np.testing.assert_allclose(gI32, gI64, rtol=1e-4, atol=1e-4)
     assert (rec32 == rec64).mean() > 0.99
+
+
+F32_CASES = [((17, 23), 1, 0.0, 2, False), ((19, 14), 1, 1.0, 2, False), ((21, 18), 3, 0.5, 1, True),
+             ((9, 11, 10), 1, 1.0, 1, False), ((8, 10, 12), 2, 0.3, 1, True), ((10, 9, 11), 1, 0.7, 1, True),
+             ((12, 7, 9), 3, 0.9, 1, False), ((30, 33), 2, 0.6, 1, False)]
+
+
+@pytest.mark.parametrize("shape,C,lam,iters,soft", F32_CASES, ids=lambda v: str(v))
+def test_f32_schedule_within_rounding_bound_of_f64(shape, C, lam, iters, soft):
+    """Direct pin of the FP32 schedule to the FP64 one (not converged: few
+    iterations).  Both compute the minimum over the same chains of the
+    sequentially rounded chain sums (addition and the min are monotone); a chain
+    has at most K = iterations * 2 * sum_a (N_a - 1) edges, each FP32 edge cost is
+    within 3 u of the exact one (difference, square, fma and root each round
+    once; the FP32 edge constant once more) and each FP32 addition rounds once,
+    so |D32 - D64| <= (K + 5) u D64 with u = 2^-24, voxel by voxel."""
+    c = synth.small_case(shape, C=C, seed=1000 + len(shape) * 10 + C, lam=lam, iterations=iters, soft=soft,
+                         v=1000.0 if soft else 1e10)
+    rng = np.random.default_rng(1001)
+    # rough (unblurred) noise: minimal paths wind, so a few iterations are far from the fixed point
+    c["image"] = rng.uniform(0.0, 4.0, size=c["image"].shape).astype(np.float32)
+    sp = tuple(float(x) for x in rng.uniform(0.5, 3.0, size=len(shape)).astype(np.float32))
+    d32 = oracle.ggdt(c["image"], c["mask"], sp, c["v"], lam, iters, "f32").astype(np.float64)
+    d64 = oracle.ggdt(c["image"].astype(np.float64), c["mask"].astype(np.float64), sp, c["v"], lam, iters, "f64")
+    K = iters * 2 * sum(n - 1 for n in shape)
+    bound = (K + 5) * 2.0 ** -24 * d64
+    err = np.abs(d32 - d64)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / np.maximum(bound, 1e-300)):.3g}"
+    assert np.array_equal(d32 == 0, d64 == 0)
+    # not converged: the check covers the schedule, not only its fixed point
+    conv = oracle.ggdt(c["image"], c["mask"], sp, c["v"], lam, iters + 3, "f32")
+    assert lam == 0.0 or not np.array_equal(conv, d32.astype(np.float32))
+
+
+@pytest.mark.parametrize("shape,C,lam,iters", [((12, 13, 11), 1, 0.7, 3), ((30, 27), 2, 0.5, 2),
+                                               ((9, 10, 8), 1, 1.0, 2), ((7, 1, 9), 1, 0.4, 2)])
+def test_incremental_f64_equals_full_forward(shape, C, lam, iters):
+    """The central-difference checker's incremental re-evaluation equals the full
+    FP64 schedule on the perturbed input bit for bit, records flag included,
+    for small perturbations and for large ones that change argmins."""
+    c = synth.small_case(shape, C=C, seed=5, lam=lam, iterations=iters, soft=True, v=10.0)
+    img, m = c["image"].astype(np.float64), c["mask"].astype(np.float64)
+    P = oracle.PerturbedF64(img, m, c["spacing"], c["v"], lam, iters)
+    D0, r0 = oracle.ggdt(img, m, c["spacing"], c["v"], lam, iters, "f64", records=True)
+    assert np.array_equal(P.base, D0) and np.array_equal(P.records, r0)
+    rng = np.random.default_rng(6)
+    changed = 0
+    for trial in range(40):
+        idx = tuple(int(rng.integers(0, s)) for s in shape)
+        which = "M" if trial % 2 == 0 else "I"
+        ch = int(rng.integers(0, C))
+        delta = (1e-3, -1e-3, 0.3, -0.5)[trial % 4]
+        D, same = P.run(which, idx, delta, ch)
+        i2, m2 = img.copy(), m.copy()
+        if which == "M":
+            m2[idx] += delta
+        else:
+            i2[(ch,) + idx] += delta
+        Df, rf = oracle.ggdt(i2, m2, c["spacing"], c["v"], lam, iters, "f64", records=True)
+        assert np.array_equal(D, Df), (trial, which, idx, delta)
+        assert same == np.array_equal(rf, r0), (trial, which, idx, delta)
+        changed += not same
+    assert 0 < changed < 40
 
 
 def test_backward_lambda0_has_no_image_gradient():
