@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import DEV, assert_parity, to_dev, to_host
+import oracle_ref
+from gpu_util import assert_parity, to_dev, to_host
 from paper_2208_00001_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -100,11 +101,15 @@ def test_gpu_gradient_vs_central_differences():
 
 def test_config5_batched_forward_backward():
     """4 x 128^3, lambda 0.7, soft mask, v = 10: one batched forward (with records)
-    and one batched backward; every volume equals its single-instance launches,
-    and volume 0 equals the oracle's FP32 forward and reverse pass."""
+    and one batched backward; for every volume the forward, the records, dL/dI and
+    dL/dM equal the oracle's FP32 forward and reverse pass bit for bit (stored
+    digests, or a live oracle run when the regenerated inputs differ), and the
+    single-instance launches give the same bits."""
     from paper_2208_00001_amd import binding as B
     from paper_2208_00001_amd.batched import BatchedPlan
     cases = synth.config5()
+    ref, nlive = oracle_ref.gradient_digests("config5", cases)
+    print(f"config5: {len(cases)} volumes, {nlive} oracle references computed live", flush=True)
     inst = [dict(image=to_dev(c["image"]), softmask=to_dev(c["mask"]), spacing=c["spacing"], v=c["v"], lam=c["lam"],
                  iterations=c["iterations"], records=True, grad_out=to_dev(c["weight"])) for c in cases]
     plan = BatchedPlan(inst)
@@ -115,15 +120,12 @@ def test_config5_batched_forward_backward():
     torch.cuda.synchronize()
     assert plan.status() == 0, "watchdog fired in the batched backward"
     for k, (c, d) in enumerate(zip(cases, plan.inst)):
+        got = {"out": to_host(d["out"]), "records": to_host(d["records"]),
+               "grad_image": to_host(grads[k][0]).reshape(c["image"].shape), "grad_mask": to_host(grads[k][1])}
+        for name, arr in got.items():
+            assert oracle_ref.sha(arr) == ref[k][name], f"volume {k}: {name} differs from the oracle"
         out, rec = B.ggdt_forward_rec(d["image"], d["softmask"], c["spacing"], c["v"], c["lam"], c["iterations"])
         gi, gm = B.ggdt_backward(d["image"], rec, d["grad_out"], c["spacing"], c["v"], c["lam"], c["iterations"])
         assert torch.equal(out, d["out"]) and torch.equal(rec, d["records"]), f"volume {k} forward"
         assert torch.equal(gi, grads[k][0]) and torch.equal(gm, grads[k][1]), f"volume {k} backward"
-    c = cases[0]
-    ref, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], c["iterations"], "f32",
-                               records=True)
-    assert np.array_equal(to_host(plan.inst[0]["out"]), ref)
-    rgi, rgm = oracle.backward(c["image"], ref_rec, c["weight"], c["spacing"], c["v"], c["lam"], c["iterations"], "f32")
-    assert assert_parity(to_host(grads[0][1]), rgm, what="dL/dM"), "dL/dM not bitwise"
-    assert assert_parity(to_host(grads[0][0]), rgi, what="dL/dI"), "dL/dI not bitwise"
     plan.close()
