@@ -84,7 +84,8 @@ int ggdt3d(const float* image, const float* softmask, const float* spacing, floa
            int iterations, float* out, int C, int D, int H, int W, void* workspace,
            size_t workspace_bytes, hipStream_t stream);
 
-/* Bytes of argmin records for the forward-with-records entries:
+/* Bytes of argmin records for the forward-with-records entries (records feed
+ * the backward below; they are not part of the paper's transform):
  * iterations * (2 * ndim) * prod(dims).  Layout: one byte per voxel per pass,
  * pass-major (pass p = iteration * 2*ndim + 2*axis + (descending ? 1 : 0)), voxels
  * row-major inside a pass.  Value 0 = the voxel kept its value in that pass;
@@ -110,9 +111,14 @@ int ggdt3d_forward_rec(const float* image, const float* softmask, const float* s
  * connected grid with the same edge costs.  Runs whole iterations (same
  * schedule and arithmetic as ggdt2d/ggdt3d) until one lowers no value, at most
  * max_iterations (>= 0); arguments otherwise as ggdt2d/ggdt3d, same workspace
- * size.  Asynchronous: the number of iterations comes from
- * ggdt_workspace_iterations.  out then equals ggdt2d/ggdt3d with that many
- * iterations (with max_iterations when it did not converge). */
+ * size.  Iterations are enqueued in blocks (4, 4, 8, 16, ...); between blocks
+ * the call synchronises `stream` and reads the workspace's done word, so it
+ * returns once the fixed point has been seen or max_iterations are enqueued,
+ * with at most one block of (immediately returning) passes after the fixed
+ * point.  It therefore cannot be captured into a HIP graph.  The number of
+ * iterations comes from ggdt_workspace_iterations.  out then equals
+ * ggdt2d/ggdt3d with that many iterations (with max_iterations when it did not
+ * converge). */
 int ggdt2d_converge(const float* image, const float* softmask, const float* spacing, float v, float lambda,
                     int max_iterations, float* out, int C, int H, int W, void* workspace,
                     size_t workspace_bytes, hipStream_t stream);
@@ -126,6 +132,12 @@ int ggdt3d_converge(const float* image, const float* softmask, const float* spac
  * max_iterations passed without reaching it.  GGDT_ERR_WATCHDOG if an
  * inter-workgroup wait of the call expired. */
 int ggdt_workspace_iterations(const void* workspace, hipStream_t stream, int* iterations);
+
+/* ------------------------------------------------------------------ backward
+ * The paper defines the forward transform only.  The argmin records and the
+ * reverse pass below are this library's addition for training use: gradients
+ * of a loss of D with respect to the image and the soft mask, obtained by
+ * running the recorded minimisations of the forward schedule in reverse. */
 
 /* Bytes of device workspace the backward entry points need: the forward's
  * workspace plus one fp32 adjoint buffer of prod(dims) values.  0 for invalid
@@ -205,7 +217,12 @@ void ggdt_set_spin_limit(unsigned long long polls);
 int ggdt_profile_begin(int n);
 int ggdt_profile_end(float* ms, int capacity);
 
-/* ------------------------------------------------------------------ batched */
+/* ------------------------------------------------------------------ batched
+ * Not from the paper, which runs one image or volume per call: this library's
+ * addition for training use.  Many instances of uneven size, each with its own
+ * spacing, v, lambda and iterations, run in one persistent launch with the
+ * same schedule and FP32 arithmetic as the plain entries (outputs equal theirs
+ * bit for bit). */
 
 /* One instance of a ragged batch.  Same meaning and layout as the plain entry
  * points; dims[2] is ignored for ndim = 2; records may be NULL (then the backward

@@ -8,7 +8,8 @@ from typing import Optional, Sequence
 
 import torch
 
-from .binding import GGDT_OK, GGDTError, GGDTInstance, GGDTTuning, _ptr, _stream, load_library
+from .binding import (GGDT_OK, GGDTError, GGDTInstance, GGDTTuning, _check_out, _check_records, _prep,
+                      _ptr, _raise_if_watchdog, _stream, load_library)
 
 
 class BatchedPlan:
@@ -25,21 +26,21 @@ class BatchedPlan:
         arr = (GGDTInstance * n)()
         self.inst = []
         for i, d in enumerate(instances):
-            m = d["softmask"]
-            img = d["image"]
-            spatial = tuple(m.shape)
-            if img.dim() == len(spatial):
-                img = img.unsqueeze(0)
-            img = img.contiguous()
-            m = m.contiguous()
+            img, m, spatial = _prep(d["image"], d["softmask"])
+            if m.device != instances[0]["softmask"].device:
+                raise ValueError(f"instance {i} is on {m.device}, instance 0 on {instances[0]['softmask'].device}")
             out = d.get("out")
             if out is None:
                 out = torch.empty(spatial, dtype=torch.float32, device=m.device)
+            else:
+                _check_out(out, spatial, m.device, what=f"instance {i} out")
             rec = d.get("records")
             if rec is True:
                 rec = torch.empty((d["iterations"] * 2 * len(spatial),) + spatial, dtype=torch.uint8, device=m.device)
             elif rec is False:
                 rec = None
+            elif rec is not None:
+                _check_records(rec, spatial, d["iterations"], m.device)
             nd = len(spatial)
             e = arr[i]
             e.ndim, e.C = nd, img.shape[0]
@@ -54,6 +55,7 @@ class BatchedPlan:
             go = d.get("grad_out")
             gi = gm = None
             if go is not None:
+                _check_out(go.contiguous(), spatial, m.device, what=f"instance {i} grad_out")
                 go = go.contiguous()
                 gi = torch.empty_like(img)
                 gm = torch.empty(spatial, dtype=torch.float32, device=m.device)
@@ -138,11 +140,17 @@ class BatchedPlan:
         except Exception:
             pass
 
+    def check(self):
+        """Synchronise and raise GGDTError if an inter-workgroup wait of the last
+        run or backward expired (the watchdog): the results are then invalid."""
+        _raise_if_watchdog(self.workspace, "batched launch")
+
 
 def ggdt_batched(instances: Sequence[dict], tuning: Optional[dict] = None):
-    """Run a ragged batch once; returns the list of distance maps."""
+    """Run a ragged batch once; returns the list of distance maps.  Synchronises,
+    and raises GGDTError if the watchdog fired."""
     plan = BatchedPlan(instances, tuning)
     out = plan.run()
-    torch.cuda.synchronize()
+    plan.check()
     plan.close()
     return out

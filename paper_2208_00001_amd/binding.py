@@ -141,6 +141,55 @@ def new_workspace(spatial, C, device) -> torch.Tensor:
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
+def _check_out(out, spatial, device, what="out"):
+    """A caller-supplied output must be exactly what the kernels write: float32,
+    contiguous, on the inputs' device, of the spatial shape (the C ABI takes no
+    buffer lengths, so a wrong size would be written past)."""
+    if out.dtype != torch.float32:
+        raise ValueError(f"{what} must be float32, got {out.dtype}")
+    if not out.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if out.device != device:
+        raise ValueError(f"{what} is on {out.device}, the inputs on {device}")
+    if tuple(out.shape) != tuple(spatial):
+        raise ValueError(f"{what} has shape {tuple(out.shape)}, expected {tuple(spatial)}")
+    return out
+
+
+def _check_records(records, spatial, iterations, device):
+    """Records: uint8, contiguous, on the device, iterations * 2 * ndim * prod(spatial) bytes."""
+    if records.dtype != torch.uint8:
+        raise ValueError(f"records must be uint8, got {records.dtype}")
+    if not records.is_contiguous():
+        raise ValueError("records must be contiguous")
+    if records.device != device:
+        raise ValueError(f"records are on {records.device}, the inputs on {device}")
+    n = int(iterations) * 2 * len(spatial)
+    for s in spatial:
+        n *= int(s)
+    if records.numel() != n:
+        raise ValueError(f"records hold {records.numel()} bytes, the schedule of {iterations} iterations needs {n}")
+    return records
+
+
+def _check_workspace(workspace, device):
+    """A caller's workspace: a contiguous uint8 tensor on the inputs' device (its
+    numel is passed as the byte count the library checks)."""
+    if workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor")
+    if workspace.device != device:
+        raise ValueError(f"workspace is on {workspace.device}, the inputs on {device}")
+    return workspace
+
+
+def _raise_if_watchdog(workspace, what):
+    """Synchronise the stream and raise if an inter-workgroup wait of the call
+    that used `workspace` expired (its results are then invalid)."""
+    rc = load_library().ggdt_workspace_status(_ptr(workspace), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, what)
+
+
 def _spacing(spacing, nd):
     sp = tuple(float(s) for s in spacing)
     if len(sp) != nd:
@@ -148,14 +197,20 @@ def _spacing(spacing, nd):
     return (ctypes.c_float * nd)(*sp)
 
 
-def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records):
+def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records, check=False):
     lib = load_library()
     image, softmask, spatial = _prep(image, softmask)
     nd, C = len(spatial), image.shape[0]
     if out is None:
         out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    else:
+        _check_out(out, spatial, softmask.device)
+    if records is not None:
+        _check_records(records, spatial, iterations, softmask.device)
     if workspace is None:
         workspace = new_workspace(spatial, C, softmask.device)
+    else:
+        _check_workspace(workspace, softmask.device)
     sp = _spacing(spacing, nd)
     args = [_ptr(image), _ptr(softmask), sp, float(v), float(lamb), int(iterations), _ptr(out)]
     if records is not None:
@@ -168,21 +223,30 @@ def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, reco
     rc = fn(*args)
     if rc != GGDT_OK:
         raise GGDTError(rc, fn.__name__)
+    if check:
+        _raise_if_watchdog(workspace, fn.__name__)
     return out
 
 
-def ggdt2d(image, softmask, spacing=(1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
-    """2D GGDT of image (C, H, W) or (H, W) with soft seed mask (H, W); returns D (H, W)."""
+def ggdt2d(image, softmask, spacing=(1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None,
+           check=False):
+    """2D GGDT of image (C, H, W) or (H, W) with soft seed mask (H, W); returns D (H, W).
+
+    Asynchronous on torch's current stream.  check=True synchronises and raises
+    GGDTError if an inter-workgroup wait expired (the watchdog); otherwise that
+    is reported only by workspace_status(workspace)."""
     if softmask.dim() != 2:
         raise ValueError("softmask must be (H, W)")
-    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None)
+    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None, check)
 
 
-def ggdt3d(image, softmask, spacing=(1.0, 1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
-    """3D GGDT of image (C, D, H, W) or (D, H, W) with soft seed mask (D, H, W); returns D."""
+def ggdt3d(image, softmask, spacing=(1.0, 1.0, 1.0), v=1e10, lamb=1.0, iterations=2, out=None, workspace=None,
+           check=False):
+    """3D GGDT of image (C, D, H, W) or (D, H, W) with soft seed mask (D, H, W); returns D.
+    check as in ggdt2d."""
     if softmask.dim() != 3:
         raise ValueError("softmask must be (D, H, W)")
-    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None)
+    return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None, check)
 
 
 def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100, out=None, workspace=None):
@@ -194,8 +258,12 @@ def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100
     nd, C = len(spatial), image.shape[0]
     if out is None:
         out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    else:
+        _check_out(out, spatial, softmask.device)
     if workspace is None:
         workspace = new_workspace(spatial, C, softmask.device)
+    else:
+        _check_workspace(workspace, softmask.device)
     fn = lib.ggdt2d_converge if nd == 2 else lib.ggdt3d_converge
     rc = fn(_ptr(image), _ptr(softmask), _spacing(spacing, nd), float(v), float(lamb), int(max_iterations),
             _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
@@ -208,55 +276,62 @@ def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100
     return out, n.value
 
 
-def _composed(kind, image, softmask, spacing, v, lamb, iterations, thetas, out, workspace):
+def _composed(kind, image, softmask, spacing, v, lamb, iterations, thetas, out, workspace, check=False):
     lib = load_library()
     image, softmask, spatial = _prep(image, softmask)
     nd, C = len(spatial), image.shape[0]
     if out is None:
         out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    else:
+        _check_out(out, spatial, softmask.device)
     if workspace is None:
         q = lib.ggdt_signed_workspace_bytes if kind == "signed" else lib.ggdt_gsf_workspace_bytes
         n = int(q(nd, _dims(spatial), C))
         if n == 0:
             raise ValueError(f"invalid shape {tuple(spatial)} with C={C}")
         workspace = torch.empty(n, dtype=torch.uint8, device=softmask.device)
+    else:
+        _check_workspace(workspace, softmask.device)
     fn = getattr(lib, f"ggdt{nd}d_{kind}")
     rc = fn(_ptr(image), _ptr(softmask), _spacing(spacing, nd), *[float(t) for t in thetas], float(v), float(lamb),
             int(iterations), _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
     if rc != GGDT_OK:
         raise GGDTError(rc, fn.__name__)
+    if check:
+        _raise_if_watchdog(workspace, fn.__name__)
     return out
 
 
-def ggdt_signed(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
-    """Signed distance D(I; M) - D(I; 1 - M) (2D or 3D by the mask's rank)."""
-    return _composed("signed", image, softmask, spacing, v, lamb, iterations, (), out, workspace)
+def ggdt_signed(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None, check=False):
+    """Signed distance D(I; M) - D(I; 1 - M) (2D or 3D by the mask's rank); check as in ggdt2d."""
+    return _composed("signed", image, softmask, spacing, v, lamb, iterations, (), out, workspace, check)
 
 
-def ggdt_gsf(image, softmask, theta_d, theta_e, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None):
-    """Geodesic symmetric filter (S_d + S_e) + (theta_e - theta_d); the filtered object is where it is < 0."""
-    return _composed("gsf", image, softmask, spacing, v, lamb, iterations, (theta_d, theta_e), out, workspace)
+def ggdt_gsf(image, softmask, theta_d, theta_e, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None,
+             check=False):
+    """Geodesic symmetric filter (S_d + S_e) + (theta_e - theta_d); the filtered object is where it is < 0.
+    check as in ggdt2d."""
+    return _composed("gsf", image, softmask, spacing, v, lamb, iterations, (theta_d, theta_e), out, workspace, check)
 
 
 def ggdt_forward_rec(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, records=None,
-                     workspace=None):
-    """Forward that also returns the argmin records, uint8 (passes, *spatial)."""
+                     workspace=None, check=False):
+    """Forward that also returns the argmin records, uint8 (passes, *spatial); check as in ggdt2d."""
     _, sm, spatial = _prep(image, softmask)
     npass = iterations * 2 * len(spatial)
     if records is None:
         records = torch.empty((npass,) + spatial, dtype=torch.uint8, device=sm.device)
-    out = _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records)
+    out = _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, records, check)
     return out, records
 
 
-def ggdt_backward(image, records, grad_out, spacing, v, lamb, iterations, workspace=None):
-    """Reverse of the recorded schedule: returns (dL/dI with image's shape, dL/dM)."""
+def ggdt_backward(image, records, grad_out, spacing, v, lamb, iterations, workspace=None, check=False):
+    """Reverse of the recorded schedule: returns (dL/dI with image's shape, dL/dM); check as in ggdt2d."""
     lib = load_library()
     squeeze = image.dim() == grad_out.dim()
     image, grad_out, spatial = _prep(image, grad_out)
     nd, C = len(spatial), image.shape[0]
-    if records.dtype != torch.uint8 or not records.is_cuda:
-        raise TypeError("records must be a uint8 device tensor")
+    _check_records(records, spatial, iterations, image.device)
     gi = torch.empty_like(image)
     gm = torch.empty(spatial, dtype=torch.float32, device=image.device)
     if workspace is None:
@@ -264,11 +339,15 @@ def ggdt_backward(image, records, grad_out, spacing, v, lamb, iterations, worksp
         if n == 0:
             raise ValueError(f"invalid shape {spatial} with C={C} for the backward")
         workspace = torch.empty(n, dtype=torch.uint8, device=image.device)
+    else:
+        _check_workspace(workspace, image.device)
     fn = lib.ggdt2d_backward if nd == 2 else lib.ggdt3d_backward
-    rc = fn(_ptr(image), _ptr(records.contiguous()), _ptr(grad_out), _spacing(spacing, nd), float(v), float(lamb),
+    rc = fn(_ptr(image), _ptr(records), _ptr(grad_out), _spacing(spacing, nd), float(v), float(lamb),
             int(iterations), _ptr(gi), _ptr(gm), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
     if rc != GGDT_OK:
         raise GGDTError(rc, fn.__name__)
+    if check:
+        _raise_if_watchdog(workspace, fn.__name__)
     return (gi[0] if squeeze else gi), gm
 
 
@@ -301,8 +380,11 @@ class GGDTFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, image, softmask, spacing, v, lamb, iterations):
-        out, rec = ggdt_forward_rec(image.detach(), softmask.detach(), spacing, v, lamb, iterations)
+        _, sm, spatial = _prep(image.detach(), softmask.detach())
+        ws = new_workspace(spatial, 1 if image.dim() == len(spatial) else image.shape[0], sm.device)
+        out, rec = ggdt_forward_rec(image.detach(), softmask.detach(), spacing, v, lamb, iterations, workspace=ws)
         ctx.save_for_backward(image.detach(), rec)
+        ctx.fwd_workspace = ws
         ctx.params = (tuple(spacing), float(v), float(lamb), int(iterations))
         return out
 
@@ -310,7 +392,10 @@ class GGDTFunction(torch.autograd.Function):
     def backward(ctx, grad_out):
         image, rec = ctx.saved_tensors
         spacing, v, lamb, iterations = ctx.params
-        gi, gm = ggdt_backward(image, rec, grad_out.contiguous().float(), spacing, v, lamb, iterations)
+        # The forward ran asynchronously: its watchdog word is read now, before
+        # its records are trusted.
+        _raise_if_watchdog(ctx.fwd_workspace, "GGDTFunction forward")
+        gi, gm = ggdt_backward(image, rec, grad_out.contiguous().float(), spacing, v, lamb, iterations, check=True)
         return gi, gm, None, None, None, None
 
 

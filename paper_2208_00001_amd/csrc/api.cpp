@@ -285,6 +285,9 @@ int build_pass(const Problem& pr, const float* image, const float* mask, const f
 
 // Convergence mode: up to max_iterations whole iterations, each followed by the
 // iteration-end kernel; passes after a no-change iteration return at once.
+// Iterations are enqueued in blocks (4, 4, 8, 16, ... iterations); after each
+// block the stream is synchronised and the done word read, so that at most one
+// block of no-op iterations follows the fixed point.
 int converge_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
                    float v, float lam, int max_iterations, float* out, void* ws, size_t wsb, hipStream_t stream) {
   if (!image || !mask || !out || !ws || !dims) return GGDT_ERR_NULL_PTR;
@@ -309,18 +312,28 @@ int converge_entry(int ndim, const int* dims, int C, const float* image, const f
   if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   unsigned base = 0;
   const int per = 2 * pr.ndim;
-  for (int it = 1; it <= max_iterations; ++it) {
-    for (int k = 0; k < per; ++k) {
-      PassDesc d;
-      rc = build_pass(pr, image, mask, spacing, v, lam, out, nullptr, (it - 1) * per + k, base, &d);
-      if (rc) return rc;
-      use_row_geometry(pr, &d);
-      d.xbuf = xbuf;
-      d.converge = 1;
-      base += (unsigned)d.nchunk + 1u;
-      if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  int block = 4;
+  for (int it = 1; it <= max_iterations;) {
+    const int last = it + block - 1 < max_iterations ? it + block - 1 : max_iterations;
+    for (; it <= last; ++it) {
+      for (int k = 0; k < per; ++k) {
+        PassDesc d;
+        rc = build_pass(pr, image, mask, spacing, v, lam, out, nullptr, (it - 1) * per + k, base, &d);
+        if (rc) return rc;
+        use_row_geometry(pr, &d);
+        d.xbuf = xbuf;
+        d.converge = 1;
+        base += (unsigned)d.nchunk + 1u;
+        if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+      }
+      if (launch_iteration_end(words, it, stream) != hipSuccess) return GGDT_ERR_HIP;
     }
-    if (launch_iteration_end(words, it, stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (it > max_iterations) break;
+    unsigned w[kWordDone + 1] = {0};
+    if (hipMemcpyAsync(w, words, sizeof w, hipMemcpyDeviceToHost, stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (w[kWordDone] || w[kWordAbort]) break;
+    if (it > 5) block *= 2;
   }
   return GGDT_OK;
 }
