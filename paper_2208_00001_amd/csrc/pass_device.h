@@ -31,6 +31,7 @@
 #pragma once
 
 #include "ggdt_internal.h"
+#include "sqrt_fix.h"
 
 namespace ggdt {
 namespace dev {
@@ -88,20 +89,10 @@ __device__ __forceinline__ int outside(int pp, int qq, int p0, int q0) {
 }
 
 // Correctly rounded square root of x in [2^-96, FLT_MAX]: the hardware root
-// (within one ulp) corrected to the nearest by the signs of the residuals
-// x - (s -+ ulp) * s.  In this range it returns the bits of sqrtf as built
-// here (the correctly rounded lowering scales only arguments below 2^-96 and
-// special-cases only zero and infinity).
-__device__ __forceinline__ float sqrt_rn_normal(float x) {
-  const float s = __builtin_amdgcn_sqrtf(x);
-  const float lo = __int_as_float(__float_as_int(s) - 1);
-  const float hi = __int_as_float(__float_as_int(s) + 1);
-  const float e_lo = fmaf(-lo, s, x);
-  const float e_hi = fmaf(-hi, s, x);
-  float r = e_lo <= 0.0f ? lo : s;
-  r = e_hi > 0.0f ? hi : r;
-  return r;
-}
+// (within one ulp) corrected to the nearest (sqrt_round_fix).  In this range it
+// returns the bits of sqrtf as built here (the correctly rounded lowering
+// scales only arguments below 2^-96 and special-cases only zero and infinity).
+__device__ __forceinline__ float sqrt_rn_normal(float x) { return sqrt_round_fix(x, __builtin_amdgcn_sqrtf(x)); }
 
 // sqrtf(x) for the general modes.
 template <int MODE>
