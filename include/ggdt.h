@@ -198,6 +198,23 @@ int ggdt3d_gsf(const float* image, const float* softmask, const float* spacing, 
                float v, float lambda, int iterations, float* out, int C, int D, int H, int W, void* workspace,
                size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory, not even a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): ggdt3d without the workspace arguments.  Its inter-workgroup
+ * scratch lives in a fixed device array of GGDT_NOALLOC_SCRATCH_BYTES inside
+ * the library (one per GPU, kept until the process ends); the call allocates
+ * nothing.  Problems whose scratch exceeds it (ggdt_workspace_bytes above
+ * GGDT_NOALLOC_SCRATCH_BYTES: planes of about 512 x 512 voxels and larger)
+ * return GGDT_ERR_WORKSPACE_TOO_SMALL before anything is enqueued.  Every
+ * call on one GPU uses that GPU's array, so calls that overlap in time on one
+ * GPU (different streams, threads) race; calls on one stream are ordered.
+ * Arguments, results, streams and errors otherwise as ggdt3d; the watchdog
+ * word cannot be queried for this entry. */
+#define GGDT_NOALLOC_SCRATCH_BYTES ((size_t)4 * 1024 * 1024 + 4096)
+int ggdt3d_noalloc(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                   int iterations, float* out, int C, int D, int H, int W, hipStream_t stream);
+
 /* After the stream has finished a call, report whether its inter-workgroup waits
  * all completed: synchronises `stream`, returns GGDT_OK or GGDT_ERR_WATCHDOG (the
  * results of that call are then invalid).  `workspace` is the one the call used. */

@@ -71,6 +71,8 @@ _SIGS = {
                             _c_int, _vp, _c_size, _vp]),
     "ggdt3d_gsf": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_float, _c_float, _c_int, _vp, _c_int, _c_int,
                             _c_int, _c_int, _vp, _c_size, _vp]),
+    "ggdt3d_noalloc": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
+                                _vp]),
     "ggdt_workspace_iterations": (_c_int, [_vp, _vp, _vp]),
     "ggdt_workspace_status": (_c_int, [_vp, _vp]),
     "ggdt_set_spin_limit": (None, [ctypes.c_ulonglong]),
