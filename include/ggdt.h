@@ -84,6 +84,28 @@ int ggdt3d(const float* image, const float* softmask, const float* spacing, floa
            int iterations, float* out, int C, int D, int H, int W, void* workspace,
            size_t workspace_bytes, hipStream_t stream);
 
+/* ----------------------------------------------- 16-bit image storage
+ * The same forward with the image stored in a 16-bit format, which halves the
+ * image bytes every pass reads (12 -> 10 bytes per voxel update for one
+ * channel).  Every value is widened to fp32 exactly on load and the transform
+ * then runs the FP32 operation sequence above unchanged, so the result equals
+ * ggdt2d/ggdt3d on the widened image bit for bit; its difference from ggdt2d/
+ * ggdt3d on the original fp32 image is the effect of rounding the image to the
+ * 16-bit format (bf16 keeps 8 significant bits, binary16 11 and a smaller
+ * range).  `image` points to 2-byte elements, layout (C, [D,] H, W) as above;
+ * `format` is GGDT_IMAGE_BF16 (bfloat16: the high half of an fp32) or
+ * GGDT_IMAGE_F16 (IEEE binary16), else GGDT_ERR_BAD_PARAM.  Supported: 2D with
+ * C <= 3 and 3D with C = 1 (GGDT_ERR_UNSUPPORTED otherwise); same workspace as
+ * ggdt2d/ggdt3d. */
+#define GGDT_IMAGE_BF16 1
+#define GGDT_IMAGE_F16 2
+int ggdt2d_half(const uint16_t* image, int format, const float* softmask, const float* spacing, float v,
+                float lambda, int iterations, float* out, int C, int H, int W, void* workspace,
+                size_t workspace_bytes, hipStream_t stream);
+int ggdt3d_half(const uint16_t* image, int format, const float* softmask, const float* spacing, float v,
+                float lambda, int iterations, float* out, int C, int D, int H, int W, void* workspace,
+                size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of argmin records for the forward-with-records entries (records feed
  * the backward below; they are not part of the paper's transform):
  * iterations * (2 * ndim) * prod(dims).  Layout: one byte per voxel per pass,

@@ -73,6 +73,10 @@ _SIGS = {
                             _c_int, _c_int, _vp, _c_size, _vp]),
     "ggdt3d_noalloc": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
                                 _vp]),
+    "ggdt2d_half": (_c_int, [_vp, _c_int, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp,
+                             _c_size, _vp]),
+    "ggdt3d_half": (_c_int, [_vp, _c_int, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
+                             _vp, _c_size, _vp]),
     "ggdt_workspace_iterations": (_c_int, [_vp, _vp, _vp]),
     "ggdt_workspace_status": (_c_int, [_vp, _vp]),
     "ggdt_set_spin_limit": (None, [ctypes.c_ulonglong]),
@@ -249,6 +253,45 @@ def ggdt3d(image, softmask, spacing=(1.0, 1.0, 1.0), v=1e10, lamb=1.0, iteration
     if softmask.dim() != 3:
         raise ValueError("softmask must be (D, H, W)")
     return _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, None, check)
+
+
+GGDT_IMAGE_BF16, GGDT_IMAGE_F16 = 1, 2
+
+
+def ggdt_half(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None, check=False):
+    """The forward with a 16-bit image: image is a torch.bfloat16 or torch.float16
+    tensor ((C,) + spatial or spatial), widened to fp32 exactly inside the kernels;
+    the result equals ggdt2d/ggdt3d on image.float() bit for bit.  2D with up to 3
+    channels, 3D with one channel.  check as in ggdt2d."""
+    lib = load_library()
+    fmt = {torch.bfloat16: GGDT_IMAGE_BF16, torch.float16: GGDT_IMAGE_F16}.get(image.dtype)
+    if fmt is None:
+        raise TypeError(f"image must be bfloat16 or float16, got {image.dtype}")
+    if not (image.is_cuda and softmask.is_cuda) or softmask.dtype != torch.float32:
+        raise ValueError("image and softmask must be device tensors, softmask float32")
+    spatial = tuple(softmask.shape)
+    if image.dim() == len(spatial):
+        image = image.unsqueeze(0)
+    if tuple(image.shape[1:]) != spatial or len(spatial) not in (2, 3):
+        raise ValueError(f"shape mismatch: image {tuple(image.shape)} vs softmask {spatial}")
+    image, softmask = image.contiguous(), softmask.contiguous()
+    nd, C = len(spatial), image.shape[0]
+    if out is None:
+        out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    else:
+        _check_out(out, spatial, softmask.device)
+    if workspace is None:
+        workspace = new_workspace(spatial, C, softmask.device)
+    else:
+        _check_workspace(workspace, softmask.device)
+    fn = lib.ggdt2d_half if nd == 2 else lib.ggdt3d_half
+    rc = fn(_ptr(image), fmt, _ptr(softmask), _spacing(spacing, nd), float(v), float(lamb), int(iterations),
+            _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    if check:
+        _raise_if_watchdog(workspace, fn.__name__)
+    return out
 
 
 def ggdt_converge(image, softmask, spacing, v=1e10, lamb=1.0, max_iterations=100, out=None, workspace=None):

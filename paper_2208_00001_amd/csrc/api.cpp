@@ -224,7 +224,7 @@ static void use_row_geometry(const Problem& pr, PassDesc* d) {
 // Enqueue the whole forward schedule of one instance.
 int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
-                    hipStream_t stream) {
+                    hipStream_t stream, int img_fmt) {
   unsigned* words = (unsigned*)ws;
   unsigned long long* xbuf = (unsigned long long*)(words + kHeaderWords);
   const long long nwords = (long long)(workspace_for(pr, tu) / 4);
@@ -234,13 +234,14 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
     return GGDT_OK;
   }
   // The image classification decides every pass's edge-cost mode on the device.
-  if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (launch_classify(image, (long long)pr.C * pr.N, words, stream, img_fmt) != hipSuccess) return GGDT_ERR_HIP;
   unsigned base = 0;
   const int npass = iterations * 2 * pr.ndim;
   for (int p = 0; p < npass; ++p) {
     PassDesc d;
     const int rc = build_pass(pr, image, mask, spacing, v, lam, out, records, p, base, &d);
     if (rc) return rc;
+    d.img_fmt = img_fmt;
     use_row_geometry(pr, &d);
     d.xbuf = xbuf;
     base += (unsigned)d.nchunk + 1u;
@@ -340,7 +341,7 @@ int converge_entry(int ndim, const int* dims, int C, const float* image, const f
 
 int forward_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
                   float v, float lam, int iterations, float* out, uint8_t* records, bool want_records, void* ws,
-                  size_t wsb, hipStream_t stream) {
+                  size_t wsb, hipStream_t stream, int img_fmt = kImgF32) {
   if (!image || !mask || !out || !ws || !dims) return GGDT_ERR_NULL_PTR;
   if (want_records && !records) return GGDT_ERR_NULL_PTR;
   Problem pr;
@@ -348,9 +349,14 @@ int forward_entry(int ndim, const int* dims, int C, const float* image, const fl
   if (rc) return rc;
   rc = check_params(ndim, spacing, v, lam, iterations);
   if (rc) return rc;
+  if (img_fmt != kImgF32) {
+    if (img_fmt != kImgBF16 && img_fmt != kImgF16) return GGDT_ERR_BAD_PARAM;
+    // kernels that read 16-bit images: single-channel volumes, images of up to kRowMaxC channels
+    if ((ndim == 3 && C != 1) || (ndim == 2 && C > kRowMaxC) || want_records) return GGDT_ERR_UNSUPPORTED;
+  }
   const Tuning tu{};
   if (wsb < workspace_for(pr, tu)) return GGDT_ERR_WORKSPACE_TOO_SMALL;
-  const size_t nb = (size_t)pr.N * 4, ni = (size_t)pr.N * pr.C * 4;
+  const size_t nb = (size_t)pr.N * 4, ni = (size_t)pr.N * pr.C * (img_fmt == kImgF32 ? 4 : 2);
   const size_t nrec = want_records ? (size_t)iterations * 2 * ndim * pr.N : 0;
   const void* ins[3] = {image, mask, ws};
   const size_t nins[3] = {ni, nb, wsb};
@@ -365,7 +371,7 @@ int forward_entry(int ndim, const int* dims, int C, const float* image, const fl
   rc = check_device();
   if (rc) return rc;
   return enqueue_forward(pr, image, mask, spacing, v, lam, iterations, out, want_records ? records : nullptr, ws,
-                         tu, stream);
+                         tu, stream, img_fmt);
 }
 
 }  // namespace ggdt
@@ -402,6 +408,26 @@ int ggdt3d(const float* image, const float* softmask, const float* spacing, floa
   const int dims[3] = {D, H, W};
   return forward_entry(3, dims, C, image, softmask, spacing, v, lambda, iterations, out, nullptr, false, workspace,
                        workspace_bytes, stream);
+}
+
+int ggdt2d_half(const uint16_t* image, int format, const float* softmask, const float* spacing, float v,
+                float lambda, int iterations, float* out, int C, int H, int W, void* workspace,
+                size_t workspace_bytes, hipStream_t stream) {
+  const int dims[2] = {H, W};
+  if (format != GGDT_IMAGE_BF16 && format != GGDT_IMAGE_F16) return GGDT_ERR_BAD_PARAM;
+  return forward_entry(2, dims, C, reinterpret_cast<const float*>(image), softmask, spacing, v, lambda, iterations,
+                       out, nullptr, false, workspace, workspace_bytes, stream,
+                       format == GGDT_IMAGE_BF16 ? kImgBF16 : kImgF16);
+}
+
+int ggdt3d_half(const uint16_t* image, int format, const float* softmask, const float* spacing, float v,
+                float lambda, int iterations, float* out, int C, int D, int H, int W, void* workspace,
+                size_t workspace_bytes, hipStream_t stream) {
+  const int dims[3] = {D, H, W};
+  if (format != GGDT_IMAGE_BF16 && format != GGDT_IMAGE_F16) return GGDT_ERR_BAD_PARAM;
+  return forward_entry(3, dims, C, reinterpret_cast<const float*>(image), softmask, spacing, v, lambda, iterations,
+                       out, nullptr, false, workspace, workspace_bytes, stream,
+                       format == GGDT_IMAGE_BF16 ? kImgBF16 : kImgF16);
 }
 
 int ggdt2d_forward_rec(const float* image, const float* softmask, const float* spacing, float v, float lambda,

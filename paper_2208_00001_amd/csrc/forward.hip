@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassDesc g, unsigned* wo
 }
 
 // Single-channel 3D passes on 16 x 16 tiles with K = 8: one thread per box cell.
-template <bool SCANC, int RMODE, bool REC>
+template <bool SCANC, int RMODE, bool REC, int FMT = kImgF32>
 __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, unsigned* words,
                                                                  unsigned long long limit) {
   __shared__ float2 pair[2 * kCellThreads];
@@ -36,17 +36,17 @@ __global__ __launch_bounds__(kCellThreads) void pass_cell_kernel(PassDesc g, uns
   }
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
-  run_pass_cell_mode<SCANC, RMODE, REC>(&g, g.xbuf, words, words + kWordClass, limit, lds,
-                                        xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+  run_pass_cell_mode<SCANC, RMODE, REC, kCellTP, kCellK, FMT>(&g, g.xbuf, words, words + kWordClass, limit, lds,
+                                                             xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // 2D passes of images with up to kRowMaxC channels: one wave per 32-cell tile.
-template <int RMODE, int NCH, bool REC>
+template <int RMODE, int NCH, bool REC, int FMT = kImgF32>
 __global__ __launch_bounds__(kRowLanes) void pass_row_kernel(PassDesc g, unsigned* words, unsigned long long limit) {
   if (ld_relaxed(words + kWordAbort) != 0u) return;
   if (g.converge && ld_relaxed(words + kWordDone) != 0u) return;  // an earlier iteration changed nothing
-  run_pass_row_mode<RMODE, NCH, REC>(&g, g.xbuf, words, words + kWordClass, limit, xcd_remap(blockIdx.x, gridDim.x),
-                                     gridDim.x);
+  run_pass_row_mode<RMODE, NCH, REC, FMT>(&g, g.xbuf, words, words + kWordClass, limit,
+                                          xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 using PassKernel = void (*)(PassDesc, unsigned*, unsigned long long);
@@ -55,21 +55,24 @@ bool use_row_path(const PassDesc& d, int ndim) {
   return ndim == 2 && d.TP == 1 && d.TQ == kRowTQ && d.K == kRowK && d.C >= 1 && d.C <= kRowMaxC && d.ntp == 1;
 }
 
-template <int NCH, bool REC>
+template <int NCH, bool REC, int FMT = kImgF32>
 PassKernel select_row_mode(int mode) {
-  if (mode == kModeLam0) return pass_row_kernel<kModeLam0, NCH, REC>;
-  if (NCH == 1 && mode == kModeLam1C1) return pass_row_kernel<kModeLam1C1, 1, REC>;
-  return pass_row_kernel<kModeGeneral, NCH, REC>;
+  if (mode == kModeLam0) return pass_row_kernel<kModeLam0, NCH, REC, FMT>;
+  if (NCH == 1 && mode == kModeLam1C1) return pass_row_kernel<kModeLam1C1, 1, REC, FMT>;
+  return pass_row_kernel<kModeGeneral, NCH, REC, FMT>;
 }
 
-template <bool REC>
+template <bool REC, int FMT = kImgF32>
 PassKernel select_row_channels(const PassDesc& d) {
-  if (d.C == 1) return select_row_mode<1, REC>(d.mode);
-  if (d.C == 2) return select_row_mode<2, REC>(d.mode);
-  return select_row_mode<3, REC>(d.mode);
+  if (d.C == 1) return select_row_mode<1, REC, FMT>(d.mode);
+  if (d.C == 2) return select_row_mode<2, REC, FMT>(d.mode);
+  return select_row_mode<3, REC, FMT>(d.mode);
 }
 
+// 16-bit images: plain forward passes only (no records).
 PassKernel select_row_kernel(const PassDesc& d) {
+  if (d.img_fmt == kImgBF16) return d.rec ? nullptr : select_row_channels<false, kImgBF16>(d);
+  if (d.img_fmt == kImgF16) return d.rec ? nullptr : select_row_channels<false, kImgF16>(d);
   return d.rec ? select_row_channels<true>(d) : select_row_channels<false>(d);
 }
 
@@ -77,8 +80,19 @@ bool use_cell_path(const PassDesc& d, int ndim) {
   return ndim == 3 && d.C == 1 && d.TP == kCellTP && d.TQ == kCellTQ && d.K == kCellK;
 }
 
+template <bool SCANC, int FMT>
+PassKernel select_cell_fmt(const PassDesc& d) {
+  if (d.rec) return nullptr;
+  if (d.mode == kModeLam0) return pass_cell_kernel<SCANC, kModeLam0, false, FMT>;
+  if (d.mode == kModeLam1C1) return pass_cell_kernel<SCANC, kModeLam1C1, false, FMT>;
+  return pass_cell_kernel<SCANC, kModeGeneral, false, FMT>;
+}
+
 template <bool SCANC>
 PassKernel select_cell_mode(const PassDesc& d) {
+  // 16-bit images: plain forward passes only (no records)
+  if (d.img_fmt == kImgBF16) return select_cell_fmt<SCANC, kImgBF16>(d);
+  if (d.img_fmt == kImgF16) return select_cell_fmt<SCANC, kImgF16>(d);
   if (d.rec) {
     if (d.mode == kModeLam0) return pass_cell_kernel<SCANC, kModeLam0, true>;
     if (d.mode == kModeLam1C1) return pass_cell_kernel<SCANC, kModeLam1C1, true>;
@@ -147,11 +161,13 @@ __global__ void reset_kernel(unsigned* ws, long long nwords) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) ws[i] = 0u;
 }
 
-__global__ __launch_bounds__(256) void classify_kernel(const float* img, long long n, unsigned* words) {
+template <int FMT>
+__global__ __launch_bounds__(256) void classify_kernel(const float* image, long long n, unsigned* words) {
+  const auto img = image_of<FMT>(image);
   unsigned bits = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float a = fabsf(img[i]);
+    const float a = fabsf(widen<FMT>(img[i]));
     if (!(a <= 0x1p60f)) bits |= kClassHuge;
     else if (a != 0.0f && a < 0x1p-40f) bits |= kClassTiny;
   }
@@ -234,6 +250,7 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
                        hipStream_t stream) {
   if (use_row_path(d, ndim)) {
     PassKernel fn = select_row_kernel(d);
+    if (!fn) return hipErrorInvalidConfiguration;
     const int cap = capacity_for(fn, 0, kRowLanes);
     if (cap <= 0) return hipErrorInvalidConfiguration;
     const int grid = d.ntq < cap ? d.ntq : cap;
@@ -242,6 +259,7 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
   }
   if (use_cell_path(d, ndim)) {
     PassKernel fn = select_cell_kernel(d);
+    if (!fn) return hipErrorInvalidConfiguration;
     const int cap = capacity_for(fn, 0, kCellThreads);
     if (cap <= 0) return hipErrorInvalidConfiguration;
     const int ntiles = d.ntp * d.ntq;
@@ -249,6 +267,7 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kCellThreads), 0, stream, d, words, spin_limit);
     return hipGetLastError();
   }
+  if (d.img_fmt != kImgF32) return hipErrorInvalidConfiguration;  // 16-bit images: cell and row kernels only
   PassKernel fn = select_kernel(d, ndim);
   if (!fn) return hipErrorInvalidConfiguration;
   const size_t lds = lds_bytes_for(ndim, d.K, d.C, d.sa == 1);
@@ -269,11 +288,13 @@ hipError_t launch_reset(unsigned* ws, long long nwords, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream) {
+hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream, int img_fmt) {
   long long blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, image, n, words);
+  auto fn = img_fmt == kImgBF16 ? classify_kernel<kImgBF16>
+                                : (img_fmt == kImgF16 ? classify_kernel<kImgF16> : classify_kernel<kImgF32>);
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, stream, image, n, words);
   return hipGetLastError();
 }
 

@@ -59,6 +59,6 @@ size_t workspace_for(const Problem& pr, const Tuning& tu);
 // already validated; ws holds at least workspace_for(pr, tu) bytes).
 int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
-                    hipStream_t stream);
+                    hipStream_t stream, int img_fmt = kImgF32);
 
 }  // namespace ggdt

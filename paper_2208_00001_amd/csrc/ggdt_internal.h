@@ -32,6 +32,15 @@ enum Mode : int {
   kModeGeneralN = 3, // the same, with the root's argument known to lie in [2^-96, FLT_MAX]
 };
 
+// Storage formats of the image.  A 16-bit format is widened to fp32 on load
+// (exactly: both are subsets of fp32) and every later step is the same FP32
+// arithmetic as for an fp32 image.
+enum ImgFmt : int {
+  kImgF32 = 0,
+  kImgBF16 = 1,  // bfloat16: the high 16 bits of an fp32
+  kImgF16 = 2,   // IEEE binary16
+};
+
 // LDS layout of the pass kernel for one tile geometry.  A chunk stages K + 1
 // planes (scan positions t0-1 .. t0+K-1) of the image and of D_old on the tile's
 // box (tile grown by K on each plane axis).  When the scan axis is the
@@ -79,6 +88,7 @@ struct PassDesc {
   unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
   int sqrt_normal;     // min_j A[j] >= 2^-96: the general root may use kModeGeneralN
   int converge;        // convergence mode: skip when done, report changes in kWordChanged
+  int img_fmt;         // ImgFmt of `image` (16-bit formats: image points to 2-byte elements)
 };
 
 // Reverse of one forward pass (see backward_device.h).  Geometry fields as in
@@ -171,7 +181,8 @@ hipError_t launch_pass(const PassDesc& d, int ndim, unsigned* words, unsigned lo
                        hipStream_t stream);
 
 hipError_t launch_reset(unsigned* ws, long long nwords, hipStream_t stream);
-hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream);
+hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream,
+                           int img_fmt = kImgF32);
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream);
 hipError_t launch_iteration_end(unsigned* words, int it, hipStream_t stream);
 

@@ -102,15 +102,18 @@ __device__ __forceinline__ CellLds carve_cell_lds(float* lds) {
   return l;
 }
 
-template <bool SCANC, int MODE, bool REC, int TT = kCellTP, int KC = kCellK>
+template <bool SCANC, int MODE, bool REC, int TT = kCellTP, int KC = kCellK, int FMT = kImgF32>
 __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                               unsigned long long limit, const CellLds& lds, int wg, int G) {
   using Geo = CellGeom<TT, KC>;
   constexpr int TP = Geo::TP, TQ = Geo::TQ, K = Geo::K, BQ = Geo::BQ, NB = Geo::NB;
   constexpr int SC = Geo::SC, SCR = Geo::SCR, STAGE = Geo::STAGE;
   const PassDesc g = *gp;
-  // global-memory views of the descriptor's arrays
-  const gmem<const float> gImage = to_gmem(g.image);
+  // global-memory views of the descriptor's arrays (the image in its storage format)
+  const gmem<const float> gImage = to_gmem(g.image);           // fp32 image
+  const gmem<const uint16_t> gImage16 = image_of<kImgBF16>(g.image);  // 16-bit image (FMT != kImgF32)
+  // the same, two positions per 32-bit word (even element offsets)
+  const gmem<const unsigned> gImage2 = (gmem<const unsigned>)(const unsigned*)(const void*)g.image;
   const gmem<const float> gMask = to_gmem(g.mask);
   const gmem<float> gD = to_gmem(g.D);
   const gmem<uint8_t> gRec = to_gmem(g.rec);
@@ -132,6 +135,15 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   const int wave0 = tid & ~63;
   // 16-byte runs need every run start 16-byte aligned
   const bool vec4s = SCANC && (Na & 3) == 0 && (g.sp & 3) == 0 && (g.sq & 3) == 0;
+  // A 16-bit image is staged by 16-byte groups of 8 positions (runs of SC16
+  // positions from a multiple of 8) when every run start is 16-byte aligned,
+  // else as 32-bit pairs of positions when it is 4-byte aligned, else it is
+  // loaded into registers.
+  constexpr int SC16 = 8 * ((K + 8 + 7) / 8);
+  const bool vec8h = SCANC && FMT != kImgF32 && (Na & 7) == 0 && (g.sp & 7) == 0 && (g.sq & 7) == 0;
+  const bool pairs16 =
+      SCANC && FMT != kImgF32 && !vec8h && (Na & 1) == 0 && (g.sp & 1) == 0 && (g.sq & 1) == 0;
+  const uint16_t* const StI16 = reinterpret_cast<const uint16_t*>(lds.stI);
 
   // First plane in scan order (never changed by the pass): written when the
   // pass initialises D, recorded as "keep" when records are asked for.
@@ -192,17 +204,36 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
 
   // Plane j of an item is used by the cells within distance kk - j of the tile.
   float nx[K + 1], nd[K + 1];
+  // A 16-bit image's raw bits: widened where consumed, so that no load of the
+  // prefetch is waited for when it is issued.
+  unsigned nxr[K + 1];
   auto fetch_regs = [&](const Item& it) {
 #pragma unroll
     for (int j = 0; j <= K; ++j) {
       const bool need = it.in && j <= it.kk && e <= it.kk - j;
       nx[j] = 0.0f;
+      nxr[j] = 0u;
       nd[j] = 0.0f;
       if (need) {
         const int x = xof(it, j);
-        if (USE_I) nx[j] = gImage[x];
+        if (USE_I) {
+          if constexpr (FMT == kImgF32)
+            nx[j] = gImage[x];
+          else
+            nxr[j] = gImage16[x];
+        }
         if (j >= 1 || it.c == 0) nd[j] = dsrc0[x];
       }
+    }
+  };
+  // A 16-bit image in the scan-contiguous layout goes to registers (2-byte
+  // loads along the cell's run), D_old through the LDS staging.
+  auto fetch_img16 = [&](const Item& it) {
+#pragma unroll
+    for (int j = 0; j <= K; ++j) {
+      const bool need = it.in && j <= it.kk && e <= it.kk - j;
+      nxr[j] = 0u;
+      if (need) nxr[j] = gImage16[xof(it, j)];
     }
   };
   auto stage = [&](const Item& it) {
@@ -230,7 +261,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
           const int x = k0 + cpp * g.sp + cqq * g.sq;
           if (max(jlo, it.c == 0 ? 0 : 1) <= jtop)
             __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + 4 * (g0 + wave0), 16, 0, 0);
-          if (USE_I && max(jlo, 0) <= jtop)
+          if (FMT == kImgF32 && USE_I && max(jlo, 0) <= jtop)
             __builtin_amdgcn_global_load_lds(gImage + x, StI + 4 * (g0 + wave0), 16, 0, 0);
         }
       }
@@ -248,7 +279,53 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
         if (ok) {
           const int x = k + cpp * g.sp + cqq * g.sq;
           if (j >= 1 || it.c == 0) __builtin_amdgcn_global_load_lds(dsrc0 + x, StD + f0 + wave0, 4, 0, 0);
-          if (USE_I) __builtin_amdgcn_global_load_lds(gImage + x, StI + f0 + wave0, 4, 0, 0);
+          if (FMT == kImgF32 && USE_I) __builtin_amdgcn_global_load_lds(gImage + x, StI + f0 + wave0, 4, 0, 0);
+        }
+      }
+    }
+    // A 16-bit image in 32-bit words of two positions: the run of a cell is SC / 2
+    // words, so the staged 16-bit elements keep the fp32 layout's indices.
+    if constexpr (FMT != kImgF32 && USE_I) {
+      if (vec8h) {
+        constexpr int GPC = SC16 / 8;  // 16-byte groups per cell
+        constexpr int NG = NB * GPC;
+        const int kmin = g.sign > 0 ? it.t0 - 1 : Na - it.t0 - it.kk;
+        const int kb16 = kmin & ~7;
+#pragma unroll
+        for (int g0 = 0; g0 < NG; g0 += NB) {
+          const int gi = g0 + stid;
+          const int lx = gi / GPC, gg = gi - lx * GPC;
+          const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+          const int cpp = it.p0 - K + cbr, cqq = it.q0 - K + cbc;
+          const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+          const int k0 = kb16 + 8 * gg;
+          const bool ok = k0 + 7 <= Na - 1 && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+          const int jlo = g.sign > 0 ? k0 - (it.t0 - 1) : (Na - it.t0) - (k0 + 7);
+          const int jtop = min(jlo + 7, it.kk - ce);
+          if (ok && max(jlo, 0) <= jtop)
+            __builtin_amdgcn_global_load_lds(gImage16 + (k0 + cpp * g.sp + cqq * g.sq), lds.stI + 4 * (g0 + wave0),
+                                             16, 0, 0);
+        }
+      }
+      if (pairs16) {
+        constexpr int GPC = SC / 2;  // words per cell
+        constexpr int NG = NB * GPC;
+#pragma unroll
+        for (int g0 = 0; g0 < NG; g0 += NB) {
+          const int gi = g0 + stid;
+          const int lx = gi / GPC, gg = gi - lx * GPC;
+          const int cbr = lx / BQ, cbc = lx - cbr * BQ;
+          const int cpp = it.p0 - K + cbr, cqq = it.q0 - K + cbc;
+          const int ce = max(max(max(K - cbr, cbr - (K + TP - 1)), max(K - cbc, cbc - (K + TQ - 1))), 0);
+          const int k0 = kb + 2 * gg;
+          const bool ok = k0 + 1 <= Na - 1 && cpp >= 0 && cpp < Np && cqq >= 0 && cqq < Nq;
+          // planes j held by this word, and the highest plane this cell needs
+          const int jlo = g.sign > 0 ? k0 - (it.t0 - 1) : (Na - it.t0) - (k0 + 1);
+          const int jtop = min(jlo + 1, it.kk - ce);
+          if (ok && max(jlo, 0) <= jtop) {
+            const int x = k0 + cpp * g.sp + cqq * g.sq;  // even
+            __builtin_amdgcn_global_load_lds(gImage2 + (x >> 1), lds.stI + (g0 + wave0), 4, 0, 0);
+          }
         }
       }
     }
@@ -256,10 +333,14 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
 
   int chg = 0;  // an own cell of this workgroup was lowered (convergence mode)
   Item cur = item_of(0);
-  if (SCANC)
+  if (SCANC) {
     stage(cur);
-  else
+    if constexpr (FMT != kImgF32 && USE_I) {
+      if (!pairs16 && !vec8h) fetch_img16(cur);
+    }
+  } else {
     fetch_regs(cur);
+  }
   for (int n = 0; n < nitems; ++n) {
     const int c = cur.c, kk = cur.kk;
     const unsigned epoch_in = g.epoch_base + (unsigned)c;  // published by chunk c - 1
@@ -273,17 +354,27 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
       __builtin_amdgcn_s_waitcnt(0);  // the global->LDS copies have landed
       __syncthreads();
       const int sbase = slot_base(cur, run_start(cur));
+      // slot of plane 0 in a 16-bit run of SC16 positions from a multiple of 8
+      const int sbase16 = slot_base(cur, (g.sign > 0 ? cur.t0 - 1 : Na - cur.t0 - cur.kk) & ~7);
 #pragma unroll
       for (int j = 0; j <= K; ++j) {
         const bool need = cur.in && j <= kk && e <= kk - j;
         const int sl = tid * SC + sbase + g.sign * j;
-        ix[j] = (USE_I && need) ? StI[sl] : 0.0f;
+        if constexpr (FMT == kImgF32)
+          ix[j] = (USE_I && need) ? StI[sl] : 0.0f;
+        else
+          ix[j] = (USE_I && need) ? widen<FMT>(vec8h ? StI16[tid * SC16 + sbase16 + g.sign * j]
+                                                    : (pairs16 ? StI16[sl] : (uint16_t)nxr[j]))
+                                  : 0.0f;
         dd[j] = (need && (j >= 1 || c == 0)) ? StD[sl] : 0.0f;
       }
     } else {
 #pragma unroll
       for (int j = 0; j <= K; ++j) {
-        ix[j] = nx[j];
+        if constexpr (FMT == kImgF32)
+          ix[j] = nx[j];
+        else
+          ix[j] = widen<FMT>((uint16_t)nxr[j]);
         dd[j] = nd[j];
       }
     }
@@ -336,6 +427,9 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
     // refilled after the steps instead: global->LDS copies in flight slow the
     // step loop down by more than their latency costs when exposed.)
     if (!SCANC && has_next) fetch_regs(nxt);
+    if constexpr (SCANC && FMT != kImgF32 && USE_I) {
+      if (has_next && !pairs16 && !vec8h) fetch_img16(nxt);
+    }
 
     // 3. The chunk's planes.
     float2* Pp = P0;
@@ -411,19 +505,19 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
 
 // Requested mode RMODE falls back to the general formula when the image
 // classification word rules the fast edge cost out.
-template <bool SCANC, int RMODE, bool REC, int TT = kCellTP, int KC = kCellK>
+template <bool SCANC, int RMODE, bool REC, int TT = kCellTP, int KC = kCellK, int FMT = kImgF32>
 __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                                    const unsigned* cls_word, unsigned long long limit,
                                                    const CellLds& lds, int wg, int G) {
   if (RMODE == kModeGeneral) {
     if (general_n_ok(gp->sqrt_normal, cls_word))
-      return run_pass_cell<SCANC, kModeGeneralN, REC, TT, KC>(gp, xbuf, words, limit, lds, wg, G);
-    return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC>(gp, xbuf, words, limit, lds, wg, G);
+      return run_pass_cell<SCANC, kModeGeneralN, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
+    return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
   }
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
-  if (fast) return run_pass_cell<SCANC, RMODE, REC, TT, KC>(gp, xbuf, words, limit, lds, wg, G);
-  return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC>(gp, xbuf, words, limit, lds, wg, G);
+  if (fast) return run_pass_cell<SCANC, RMODE, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
+  return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
 }
 
 // Layout and requested mode chosen at run time (batched launches).

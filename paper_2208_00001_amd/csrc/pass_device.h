@@ -57,6 +57,31 @@ __device__ __forceinline__ gmem<T> to_gmem(T* p) {
   return (gmem<T>)p;
 }
 
+// Element type of an image format and its exact widening to fp32.
+template <int FMT>
+struct ImgElem {
+  using T = float;
+};
+template <>
+struct ImgElem<kImgBF16> {
+  using T = uint16_t;
+};
+template <>
+struct ImgElem<kImgF16> {
+  using T = uint16_t;
+};
+template <int FMT>
+__device__ __forceinline__ float widen(typename ImgElem<FMT>::T v) {
+  if constexpr (FMT == kImgBF16) return __uint_as_float((unsigned)v << 16);
+  else if constexpr (FMT == kImgF16) return (float)__builtin_bit_cast(_Float16, v);
+  else return v;
+}
+// The image of a pass descriptor as an array of its storage format.
+template <int FMT>
+__device__ __forceinline__ gmem<const typename ImgElem<FMT>::T> image_of(const float* image) {
+  return (gmem<const typename ImgElem<FMT>::T>)(const typename ImgElem<FMT>::T*)(const void*)image;
+}
+
 __device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -45,14 +45,14 @@ __device__ __forceinline__ float row_edge(const PassDesc& g, int j, const float*
 
 // One 2D pass of an image with NCH channels (the image is not read when MODE is
 // kModeLam0), run by workgroup `wg` of G single-wave workgroups.
-template <int MODE, int NCH, bool REC>
+template <int MODE, int NCH, bool REC, int FMT = kImgF32>
 __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                              unsigned long long limit, int wg, int G) {
   constexpr int K = kRowK, TQ = kRowTQ;
   constexpr bool USE_I = MODE != kModeLam0;
   constexpr int NI = USE_I ? NCH : 1;
   const PassDesc g = *gp;
-  const gmem<const float> gImage = to_gmem(g.image);
+  const auto gImage = image_of<FMT>(g.image);  // read widened to fp32
   const gmem<const float> gMask = to_gmem(g.mask);
   const gmem<float> gD = to_gmem(g.D);
   const gmem<uint8_t> gRec = to_gmem(g.rec);
@@ -108,10 +108,15 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
   // address) and keeps the value only where it is needed: no branch.  Row j
   // lies sign * sa elements after row j - 1.
   float nd[K + 1], nx[K + 1][NI];
+  // A 16-bit image's raw bits and the last row the lane needs: widened and
+  // selected where consumed, so that no load of the prefetch is waited for.
+  unsigned nxr[K + 1][NI];
+  int nlast = -1;
   auto fetch = [&](const Item& it) {
     const int x0 = xof(it, 0);
     const int step = g.sign * g.sa;
     const int last = it.in ? it.kk - e : -1;  // the lane needs rows 0 .. last
+    nlast = last;
 #pragma unroll
     for (int j = 0; j <= K; ++j) {
       const bool need = j <= last;
@@ -124,8 +129,12 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
       if (USE_I) {
 #pragma unroll
         for (int c = 0; c < NI; ++c) {
-          const float iv = gImage[c * cstride + x];
-          nx[j][c] = need ? iv : 0.0f;
+          if constexpr (FMT == kImgF32) {
+            const float iv = gImage[c * cstride + x];
+            nx[j][c] = need ? iv : 0.0f;
+          } else {
+            nxr[j][c] = gImage[c * cstride + x];
+          }
         }
       } else {
         nx[j][0] = 0.0f;
@@ -147,7 +156,12 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
     for (int j = 0; j <= K; ++j) {
       dd[j] = nd[j] * vscale;  // the initialising pass reads the mask: D_old = v * M
 #pragma unroll
-      for (int ch = 0; ch < NI; ++ch) ix[j][ch] = nx[j][ch];
+      for (int ch = 0; ch < NI; ++ch) {
+        if constexpr (FMT == kImgF32 || !USE_I)
+          ix[j][ch] = nx[j][ch];
+        else
+          ix[j][ch] = j <= nlast ? widen<FMT>((uint16_t)nxr[j][ch]) : 0.0f;
+      }
     }
 
     // Row 0 of the chunk: the pass's first row in chunk 0, else the values the
@@ -262,18 +276,18 @@ __device__ __forceinline__ bool run_pass_row(const PassDesc* gp, unsigned long l
 
 // Requested mode RMODE falls back to the general formula when the image
 // classification word rules the fast edge cost out.
-template <int RMODE, int NCH, bool REC>
+template <int RMODE, int NCH, bool REC, int FMT = kImgF32>
 __device__ __forceinline__ bool run_pass_row_mode(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                                   const unsigned* cls_word, unsigned long long limit, int wg, int G) {
   if (RMODE == kModeGeneral) {
     if (general_n_ok(gp->sqrt_normal, cls_word))
-      return run_pass_row<kModeGeneralN, NCH, REC>(gp, xbuf, words, limit, wg, G);
-    return run_pass_row<kModeGeneral, NCH, REC>(gp, xbuf, words, limit, wg, G);
+      return run_pass_row<kModeGeneralN, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
+    return run_pass_row<kModeGeneral, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
   }
   const unsigned cls = ld_relaxed(cls_word);
   const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
-  if (fast) return run_pass_row<RMODE, NCH, REC>(gp, xbuf, words, limit, wg, G);
-  return run_pass_row<kModeGeneral, NCH, REC>(gp, xbuf, words, limit, wg, G);
+  if (fast) return run_pass_row<RMODE, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
+  return run_pass_row<kModeGeneral, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
 }
 
 }  // namespace dev

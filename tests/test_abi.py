@@ -176,3 +176,22 @@ def test_workspace_covers_2d_row_tiles(lib):
             for nq in (W, H):  # row length of the axis-0 and axis-1 passes
                 need = 256 + 2 * (-(-nq // 32)) * 32 * 8
                 assert ws >= need, (H, W, C, ws, need)
+
+
+def test_half_image_validation_codes(lib):
+    """ggdt{2,3}d_half reject a bad format, unsupported geometries and the usual
+    invalid arguments before touching the device (fake pointers)."""
+    def call(ndim, fmt=1, C=1, image=FAKE, lam=1.0, dims=(8, 9, 10)):
+        sp = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+        ws = FAKE + (3 << 30)
+        if ndim == 3:
+            return lib.ggdt3d_half(ctypes.c_void_p(image), fmt, ctypes.c_void_p(FAKE + (1 << 30)), sp, 1e10, lam, 1,
+                                   ctypes.c_void_p(FAKE + (2 << 30)), C, *dims, ctypes.c_void_p(ws), 1 << 24, None)
+        return lib.ggdt2d_half(ctypes.c_void_p(image), fmt, ctypes.c_void_p(FAKE + (1 << 30)), sp, 1e10, lam, 1,
+                               ctypes.c_void_p(FAKE + (2 << 30)), C, *dims[:2], ctypes.c_void_p(ws), 1 << 24, None)
+    assert call(3, fmt=0) == -3 and call(3, fmt=3) == -3 and call(2, fmt=7) == -3
+    assert call(3, C=2) == -8          # volumes: one channel
+    assert call(2, C=4) == -8          # images: up to three channels
+    assert call(3, image=0) == -1
+    assert call(3, lam=2.0) == -3
+    assert call(2, C=0) == -2
