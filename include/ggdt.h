@@ -65,12 +65,20 @@ extern "C" {
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* ggdt_strerror(int status);
 
-/* Bytes of device workspace the forward and backward entry points need for a
- * problem of `ndim` (2 or 3) spatial dims `dims` (array-axis order) and C
- * channels.  Returns 0 for invalid shapes.  The workspace holds inter-workgroup
- * progress flags, the image classification word and the watchdog word; its
- * content need not be initialised by the caller. */
+/* Bytes of device workspace the forward entry points (plain, records,
+ * fixed point, 16-bit image) use for a problem of `ndim` (2 or 3) spatial dims
+ * `dims` (array-axis order) and C channels.  Returns 0 for invalid shapes.  The
+ * workspace holds inter-workgroup progress flags, the image classification
+ * word and the watchdog word; its content need not be initialised by the
+ * caller.  For single-channel volumes it also holds copies of D and of the
+ * image laid out [W][D][H] (the last axis slowest), on which the passes along
+ * the last axis run as strided passes (a library addition; the passes compute
+ * the same values).  ggdt_workspace_min_bytes is the smallest size the
+ * forward accepts: with less than ggdt_workspace_bytes it runs those passes in
+ * place, more slowly.  The two are equal for images and multi-channel
+ * volumes. */
 size_t ggdt_workspace_bytes(int ndim, const int* dims, int C);
+size_t ggdt_workspace_min_bytes(int ndim, const int* dims, int C);
 
 /* Plain forward, 2D: out = GGDT(image, softmask) after `iterations` iterations of
  * the four passes.  iterations = 0 writes v * softmask.  `out` must not overlap
@@ -199,8 +207,11 @@ int ggdt3d_backward(const float* image, const uint8_t* records, const float* gra
  * workspace.  theta_d, theta_e must be finite and >= 0 (else
  * GGDT_ERR_BAD_PARAM). */
 
-/* Workspace bytes: the transform's workspace plus 2 (signed) or 4 (GSF) fp32
- * buffers of prod(dims) values.  0 for invalid shapes. */
+/* Workspace bytes: the transform's minimal workspace plus 2 (signed) or 4
+ * (GSF) fp32 buffers of prod(dims) values, plus, for single-channel volumes,
+ * the scan-major copies described at ggdt_workspace_bytes (without them,
+ * i.e. with 2 x prod(dims) x 4 bytes less, rounded to 256-byte multiples, the
+ * passes along the last axis run in place).  0 for invalid shapes. */
 size_t ggdt_signed_workspace_bytes(int ndim, const int* dims, int C);
 size_t ggdt_gsf_workspace_bytes(int ndim, const int* dims, int C);
 
@@ -226,7 +237,8 @@ int ggdt3d_gsf(const float* image, const float* softmask, const float* spacing, 
  * allocation): ggdt3d without the workspace arguments.  Its inter-workgroup
  * scratch lives in a fixed device array of GGDT_NOALLOC_SCRATCH_BYTES inside
  * the library (one per GPU, kept until the process ends); the call allocates
- * nothing.  Problems whose scratch exceeds it (ggdt_workspace_bytes above
+ * nothing; the passes run in place (no scan-major copies).  Problems whose
+ * scratch exceeds it (ggdt_workspace_min_bytes above
  * GGDT_NOALLOC_SCRATCH_BYTES: planes of about 512 x 512 voxels and larger)
  * return GGDT_ERR_WORKSPACE_TOO_SMALL before anything is enqueued.  Every
  * call on one GPU uses that GPU's array, so calls that overlap in time on one

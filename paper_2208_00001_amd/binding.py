@@ -44,6 +44,7 @@ _lib = None
 _SIGS = {
     "ggdt_strerror": (ctypes.c_char_p, [_c_int]),
     "ggdt_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt_workspace_min_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt_records_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt_backward_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt2d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp, _c_size, _vp]),
@@ -135,13 +136,20 @@ def workspace_bytes(spatial: Sequence[int], C: int) -> int:
     return int(lib.ggdt_workspace_bytes(len(spatial), _dims(spatial), C))
 
 
+def workspace_min_bytes(spatial: Sequence[int], C: int) -> int:
+    """Smallest forward workspace: single-channel volumes then run the passes
+    along the last axis in place instead of on scan-major copies."""
+    lib = load_library()
+    return int(lib.ggdt_workspace_min_bytes(len(spatial), _dims(spatial), C))
+
+
 def records_bytes(spatial: Sequence[int], iterations: int) -> int:
     lib = load_library()
     return int(lib.ggdt_records_bytes(len(spatial), _dims(spatial), iterations))
 
 
-def new_workspace(spatial, C, device) -> torch.Tensor:
-    n = workspace_bytes(spatial, C)
+def new_workspace(spatial, C, device, minimal=False) -> torch.Tensor:
+    n = workspace_min_bytes(spatial, C) if minimal else workspace_bytes(spatial, C)
     if n == 0:
         raise ValueError(f"invalid shape {tuple(spatial)} with C={C}")
     return torch.empty(n, dtype=torch.uint8, device=device)
@@ -214,7 +222,8 @@ def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, reco
     if records is not None:
         _check_records(records, spatial, iterations, softmask.device)
     if workspace is None:
-        workspace = new_workspace(spatial, C, softmask.device)
+        # a forward with records keeps every pass in place: no scan-major copies
+        workspace = new_workspace(spatial, C, softmask.device, minimal=records is not None)
     else:
         _check_workspace(workspace, softmask.device)
     sp = _spacing(spacing, nd)
@@ -426,7 +435,7 @@ class GGDTFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, image, softmask, spacing, v, lamb, iterations):
         _, sm, spatial = _prep(image.detach(), softmask.detach())
-        ws = new_workspace(spatial, 1 if image.dim() == len(spatial) else image.shape[0], sm.device)
+        ws = new_workspace(spatial, 1 if image.dim() == len(spatial) else image.shape[0], sm.device, minimal=True)
         out, rec = ggdt_forward_rec(image.detach(), softmask.detach(), spacing, v, lamb, iterations, workspace=ws)
         ctx.save_for_backward(image.detach(), rec)
         ctx.fwd_workspace = ws

@@ -208,6 +208,28 @@ size_t workspace_for(const Problem& pr, const Tuning& tu) {
   return (size_t)kHeaderWords * 4 + xbuf;
 }
 
+// Bytes of the scan-major copies (D, then the image, each 256-byte aligned)
+// through which the passes along the last axis of a single-channel volume run
+// as strided passes; 0 where the forward keeps those passes in place.
+size_t scan_major_bytes(const Problem& pr) {
+  if (pr.ndim != 3 || pr.C != 1 || pr.dims[2] < 2) return 0;
+  return 2 * (((size_t)pr.N * 4 + 255) / 256 * 256);
+}
+
+// The pass along axis 2 on the scan-major copies ([W][D][H]: the scan axis
+// slowest, H contiguous).  The plane axes keep their order (p = axis 0, q =
+// axis 1), so tiles, offsets j and edge constants are those of the pass on the
+// C-order volume.
+static void use_scan_major(const Problem& pr, const void* image_t, float* d_t, PassDesc* d) {
+  d->sa = pr.dims[0] * pr.dims[1];
+  d->sp = pr.dims[1];
+  d->sq = 1;
+  d->image = static_cast<const float*>(image_t);
+  d->D = d_t;
+  d->K = pass_chunk_for(pr.ndim, pr.C, d->sa == 1);
+  d->nchunk = (d->Na - 1 + d->K - 1) / d->K;
+}
+
 // 2D passes of images with up to kRowMaxC channels run on the row kernel
 // (one wave per 32-cell tile, chunks of 16 rows).  Its exchange area,
 // ceil(Nq / 32) * 32 words per parity, fits in the tile kernel's.
@@ -224,7 +246,7 @@ static void use_row_geometry(const Problem& pr, PassDesc* d) {
 // Enqueue the whole forward schedule of one instance.
 int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
-                    hipStream_t stream, int img_fmt) {
+                    hipStream_t stream, int img_fmt, void* scan_major) {
   unsigned* words = (unsigned*)ws;
   unsigned long long* xbuf = (unsigned long long*)(words + kHeaderWords);
   const long long nwords = (long long)(workspace_for(pr, tu) / 4);
@@ -235,6 +257,11 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
   }
   // The image classification decides every pass's edge-cost mode on the device.
   if (launch_classify(image, (long long)pr.C * pr.N, words, stream, img_fmt) != hipSuccess) return GGDT_ERR_HIP;
+  const ScanMajor sm = scan_major_for(pr, records, scan_major);
+  const int esz = img_fmt == kImgF32 ? 4 : 2;
+  if (sm.on && launch_to_scan_major(image, sm.image, esz, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) !=
+                   hipSuccess)
+    return GGDT_ERR_HIP;
   unsigned base = 0;
   const int npass = iterations * 2 * pr.ndim;
   for (int p = 0; p < npass; ++p) {
@@ -245,10 +272,29 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
     use_row_geometry(pr, &d);
     d.xbuf = xbuf;
     base += (unsigned)d.nchunk + 1u;
+    const int k = p % (2 * pr.ndim);
+    if (sm.on && k >= 4) use_scan_major(pr, sm.image, sm.D, &d);
+    if (sm.on && k == 4 &&
+        launch_to_scan_major(out, sm.D, 4, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) != hipSuccess)
+      return GGDT_ERR_HIP;
     if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (sm.on && k == 5 &&
+        launch_from_scan_major(sm.D, out, 4, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) != hipSuccess)
+      return GGDT_ERR_HIP;
   }
   (void)tu;
   return GGDT_OK;
+}
+
+ScanMajor scan_major_for(const Problem& pr, const uint8_t* records, void* buf) {
+  ScanMajor sm{};
+  // Records are stored per voxel in C order, so a forward with records keeps
+  // every pass in place.
+  if (!buf || records || scan_major_bytes(pr) == 0) return sm;
+  sm.on = true;
+  sm.D = static_cast<float*>(buf);
+  sm.image = static_cast<unsigned char*>(buf) + scan_major_bytes(pr) / 2;
+  return sm;
 }
 
 int build_pass(const Problem& pr, const float* image, const float* mask, const float* spacing, float v, float lam,
@@ -311,6 +357,10 @@ int converge_entry(int ndim, const int* dims, int C, const float* image, const f
   if (launch_reset(words, (long long)(workspace_for(pr, tu) / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (max_iterations == 0) return launch_scale(mask, v, out, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
   if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+  const ScanMajor sm = scan_major_for(pr, nullptr, scan_major_in(pr, tu, ws, wsb));
+  if (sm.on && launch_to_scan_major(image, sm.image, 4, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) !=
+                   hipSuccess)
+    return GGDT_ERR_HIP;
   unsigned base = 0;
   const int per = 2 * pr.ndim;
   int block = 4;
@@ -325,7 +375,17 @@ int converge_entry(int ndim, const int* dims, int C, const float* image, const f
         d.xbuf = xbuf;
         d.converge = 1;
         base += (unsigned)d.nchunk + 1u;
+        // the layout changes do nothing once the done word is set, as the passes
+        if (sm.on && k >= 4) use_scan_major(pr, sm.image, sm.D, &d);
+        if (sm.on && k == 4 &&
+            launch_to_scan_major(out, sm.D, 4, pr.dims[0], pr.dims[1], pr.dims[2], words + kWordDone, stream) !=
+                hipSuccess)
+          return GGDT_ERR_HIP;
         if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+        if (sm.on && k == 5 &&
+            launch_from_scan_major(sm.D, out, 4, pr.dims[0], pr.dims[1], pr.dims[2], words + kWordDone, stream) !=
+                hipSuccess)
+          return GGDT_ERR_HIP;
       }
       if (launch_iteration_end(words, it, stream) != hipSuccess) return GGDT_ERR_HIP;
     }
@@ -371,7 +431,13 @@ int forward_entry(int ndim, const int* dims, int C, const float* image, const fl
   rc = check_device();
   if (rc) return rc;
   return enqueue_forward(pr, image, mask, spacing, v, lam, iterations, out, want_records ? records : nullptr, ws,
-                         tu, stream, img_fmt);
+                         tu, stream, img_fmt, scan_major_in(pr, tu, ws, wsb));
+}
+
+void* scan_major_in(const Problem& pr, const Tuning& tu, void* ws, size_t wsb) {
+  const size_t base = workspace_for(pr, tu), extra = scan_major_bytes(pr);
+  if (extra == 0 || wsb < base + extra) return nullptr;
+  return static_cast<unsigned char*>(ws) + base;
 }
 
 }  // namespace ggdt
@@ -383,6 +449,13 @@ extern "C" {
 const char* ggdt_strerror(int status) { return status_text(status); }
 
 size_t ggdt_workspace_bytes(int ndim, const int* dims, int C) {
+  if (!dims) return 0;
+  Problem pr;
+  if (make_problem(ndim, dims, C, &pr)) return 0;
+  return workspace_for(pr, Tuning{}) + scan_major_bytes(pr);
+}
+
+size_t ggdt_workspace_min_bytes(int ndim, const int* dims, int C) {
   if (!dims) return 0;
   Problem pr;
   if (make_problem(ndim, dims, C, &pr)) return 0;

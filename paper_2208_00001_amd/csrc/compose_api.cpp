@@ -15,9 +15,16 @@ namespace {
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Workspace: the transform's header and exchange words, then nbuf fp32
-// buffers of N values, each 256-byte aligned.
+// buffers of N values, each 256-byte aligned, then (optional) the scan-major
+// copies of the transform.
 size_t compose_workspace(const Problem& pr, int nbuf) {
   return align256(workspace_for(pr, Tuning{})) + (size_t)nbuf * align256((size_t)pr.N * 4);
+}
+
+void* scan_major_area(const Problem& pr, int nbuf, void* ws, size_t wsb) {
+  const size_t base = compose_workspace(pr, nbuf), extra = scan_major_bytes(pr);
+  if (extra == 0 || wsb < base + extra) return nullptr;
+  return static_cast<unsigned char*>(ws) + base;
 }
 
 float* buffer(void* ws, const Problem& pr, int i) {
@@ -27,12 +34,13 @@ float* buffer(void* ws, const Problem& pr, int i) {
 
 // dst = D(I; mask) - D(I; 1 - mask); tmp_a, tmp_b: N-value scratch buffers.
 int enqueue_signed(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
-                   float lam, int iterations, float* dst, float* tmp_a, float* tmp_b, void* ws, hipStream_t stream) {
+                   float lam, int iterations, float* dst, float* tmp_a, float* tmp_b, void* ws, void* sm,
+                   hipStream_t stream) {
   const Tuning tu{};
-  int rc = enqueue_forward(pr, image, mask, spacing, v, lam, iterations, dst, nullptr, ws, tu, stream);
+  int rc = enqueue_forward(pr, image, mask, spacing, v, lam, iterations, dst, nullptr, ws, tu, stream, kImgF32, sm);
   if (rc) return rc;
   if (launch_compose(kOpComplement, mask, nullptr, 0.0f, tmp_a, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
-  rc = enqueue_forward(pr, image, tmp_a, spacing, v, lam, iterations, tmp_b, nullptr, ws, tu, stream);
+  rc = enqueue_forward(pr, image, tmp_a, spacing, v, lam, iterations, tmp_b, nullptr, ws, tu, stream, kImgF32, sm);
   if (rc) return rc;
   if (launch_compose(kOpSub, dst, tmp_b, 0.0f, dst, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
   return GGDT_OK;
@@ -62,7 +70,7 @@ int signed_entry(int ndim, const int* dims, int C, const float* image, const flo
   const int rc = validate(ndim, dims, C, image, mask, spacing, v, lam, iterations, out, ws, wsb, 2, &pr);
   if (rc) return rc;
   return enqueue_signed(pr, image, mask, spacing, v, lam, iterations, out, buffer(ws, pr, 0), buffer(ws, pr, 1), ws,
-                        stream);
+                        scan_major_area(pr, 2, ws, wsb), stream);
 }
 
 int gsf_entry(int ndim, const int* dims, int C, const float* image, const float* mask, const float* spacing,
@@ -76,16 +84,17 @@ int gsf_entry(int ndim, const int* dims, int C, const float* image, const float*
   float* w2 = buffer(ws, pr, 1);
   float* w3 = buffer(ws, pr, 2);
   float* w4 = buffer(ws, pr, 3);
+  void* sm = scan_major_area(pr, 4, ws, wsb);
   // S0 = S(M) -> w1
-  rc = enqueue_signed(pr, image, mask, spacing, v, lam, iterations, w1, w2, w3, ws, stream);
+  rc = enqueue_signed(pr, image, mask, spacing, v, lam, iterations, w1, w2, w3, ws, sm, stream);
   if (rc) return rc;
   // dilated object {S0 < theta_d} -> w2; its signed distance S_d -> out
   if (launch_compose(kOpObjectMask, w1, nullptr, theta_d, w2, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
-  rc = enqueue_signed(pr, image, w2, spacing, v, lam, iterations, out, w3, w4, ws, stream);
+  rc = enqueue_signed(pr, image, w2, spacing, v, lam, iterations, out, w3, w4, ws, sm, stream);
   if (rc) return rc;
   // eroded object {S0 < -theta_e} -> w1 (in place); its signed distance S_e -> w2
   if (launch_compose(kOpObjectMask, w1, nullptr, -theta_e, w1, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
-  rc = enqueue_signed(pr, image, w1, spacing, v, lam, iterations, w2, w3, w4, ws, stream);
+  rc = enqueue_signed(pr, image, w1, spacing, v, lam, iterations, w2, w3, w4, ws, sm, stream);
   if (rc) return rc;
   // (S_d + S_e) + (theta_e - theta_d)
   const float shift = theta_e - theta_d;
@@ -97,7 +106,7 @@ size_t workspace_query(int ndim, const int* dims, int C, int nbuf) {
   if (!dims) return 0;
   Problem pr;
   if (make_problem(ndim, dims, C, &pr)) return 0;
-  return compose_workspace(pr, nbuf);
+  return compose_workspace(pr, nbuf) + scan_major_bytes(pr);
 }
 
 }  // namespace

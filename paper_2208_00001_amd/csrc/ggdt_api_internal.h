@@ -55,10 +55,25 @@ int max_tiles(const Problem& pr, const Tuning& tu);
 int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,
                    float* gI, int p, int K, unsigned epoch_base, BwdDesc* d);
 size_t workspace_for(const Problem& pr, const Tuning& tu);
+// Scan-major copies of D and of the image for the passes along the last axis
+// of a single-channel volume (see layout.hip).
+size_t scan_major_bytes(const Problem& pr);
+struct ScanMajor {
+  bool on;
+  float* D;     // D laid out [W][D][H]
+  void* image;  // the image in its storage format, laid out [W][D][H]
+};
+// The copies in `buf` (scan_major_bytes(pr) bytes), if the schedule uses them.
+ScanMajor scan_major_for(const Problem& pr, const uint8_t* records, void* buf);
+// The scan-major area of a forward workspace of wsb bytes (after the first
+// workspace_for(pr, tu) bytes), or null if the workspace has no room for it.
+void* scan_major_in(const Problem& pr, const Tuning& tu, void* ws, size_t wsb);
 // Enqueue the whole forward schedule of one instance on `stream` (arguments
-// already validated; ws holds at least workspace_for(pr, tu) bytes).
+// already validated; ws holds at least workspace_for(pr, tu) bytes).  With
+// `scan_major` (scan_major_bytes(pr) bytes, or null) the passes along the last
+// axis of a single-channel volume without records run on scan-major copies.
 int enqueue_forward(const Problem& pr, const float* image, const float* mask, const float* spacing, float v,
                     float lam, int iterations, float* out, uint8_t* records, void* ws, const Tuning& tu,
-                    hipStream_t stream, int img_fmt = kImgF32);
+                    hipStream_t stream, int img_fmt = kImgF32, void* scan_major = nullptr);
 
 }  // namespace ggdt

@@ -148,3 +148,23 @@ def test_config3_3d_256():
         if _digest(got) == ref["out_sha256"]:
             return
     check_case(c)
+
+
+@pytest.mark.parametrize("shape,lam,it", [((37, 41, 29), 1.0, 2), ((20, 33, 70), 0.3, 2), ((17, 16, 66), 0.0, 1),
+                                          ((3, 65, 131), 0.8, 2), ((1, 1, 40), 0.5, 2), ((70, 2, 9), 1.0, 3)],
+                         ids=lambda v: str(v))
+def test_scan_major_and_in_place_last_axis(shape, lam, it):
+    """Single-channel volumes: the passes along the last axis on the scan-major
+    copies (full workspace) and in place (the minimal workspace) both equal the
+    oracle bit for bit."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=1, seed=sum(shape), lam=lam, iterations=it)
+    ref = oracle_forward(c)
+    assert B.workspace_bytes(shape, 1) > B.workspace_min_bytes(shape, 1)
+    img, m = to_dev(c["image"]), to_dev(c["mask"])
+    for minimal in (False, True):
+        print(f"case {shape} lam={lam} it={it} minimal={minimal}", flush=True)
+        ws = B.new_workspace(shape, 1, DEV, minimal=minimal)
+        got = to_host(B.ggdt3d(img, m, c["spacing"], c["v"], c["lam"], c["iterations"], workspace=ws))
+        assert B.workspace_status(ws) == 0, "watchdog fired"
+        assert assert_parity(got, ref, what=f"{shape} minimal={minimal}"), "not bitwise"
