@@ -73,7 +73,7 @@ def traffic_from_counters(n_voxels):
     return s.get("hbm_bytes_per_pass_launch")
 
 
-def cpu_baseline(c):
+def cpu_baseline(c, toiv_gpu=None):
     import oracle
     t = time.perf_counter()
     oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
@@ -89,11 +89,11 @@ def cpu_baseline(c):
     dt = time.perf_counter() - t
     out["openmp"] = {"value": vu / dt, "unit": "voxel-updates/s", "cores": threads,
                      "sample": f"the same iteration in {dt:.2f} s"}
-    out["toivanen"] = toivanen_comparison(c)
+    out["toivanen"] = toivanen_comparison(c, toiv_gpu)
     return out
 
 
-def toivanen_comparison(c):
+def toivanen_comparison(c, toiv_gpu=None):
     """Toivanen's sequential raster scan (the paper's comparison method, one
     thread): its rate on one iteration of the volume (two raster sweeps over
     half of the 26-neighbourhood), and the iterations each method needs to
@@ -101,10 +101,12 @@ def toivanen_comparison(c):
     import oracle
     from paper_2208_00001_amd import synth
     t = time.perf_counter()
-    oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
+    ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
     dt = time.perf_counter() - t
     res = {"voxel_visits_per_s": 2 * c["mask"].size / dt, "cores": 1,
            "sample": f"1 iteration (2 sweeps) of the {c['name']} volume in {dt:.1f} s", "iterations_to_fixed_point": {}}
+    if toiv_gpu is not None:
+        res["gpu_output_equals_oracle"] = bool((toiv_gpu.view("u4") == ref.view("u4")).all())
     for cc in (synth.config1(1.0), synth.config1(0.0), synth.config3(size=64)):
         _, n_scan = oracle.until_converged(cc["image"], cc["mask"], cc["spacing"], cc["v"], cc["lam"])
         _, n_toiv = oracle.toivanen(cc["image"], cc["mask"], cc["spacing"], cc["v"], cc["lam"], 10000, "f32",
@@ -418,6 +420,30 @@ def bench_half(c, img, m, out32, reps):
     return res
 
 
+def bench_toivanen(c, img, m, reps):
+    """Toivanen's raster scan on the GPU (hyperplane sweeps, one persistent
+    launch) on the benchmark volume: one iteration (a forward and a backward
+    sweep over half of the 26-neighbourhood each).  Returns the line's entry and
+    the output, which the CPU leg compares with the oracle's sequential sweeps."""
+    import numpy as np
+    import torch
+
+    from paper_2208_00001_amd import binding as B
+    out = torch.empty_like(m)
+    ws = B.new_workspace(tuple(m.shape), 1, img.device, minimal=True)
+
+    def run():
+        B.ggdt_toivanen(img, m, c["spacing"], c["v"], c["lam"], 1, out=out, workspace=ws)
+
+    ms = _time(run, reps)
+    assert B.workspace_status(ws) == 0, "watchdog fired (Toivanen)"
+    N = int(np.prod(tuple(m.shape)))
+    res = {"workload": c["name"] + ", Toivanen's raster scan, 1 iteration (2 sweeps)", "ms": ms,
+           "voxel_visits_per_s": 2 * N / (ms * 1e-3),
+           "hyperplanes_per_sweep": 4 * (m.shape[0] - 1) + 2 * (m.shape[1] - 1) + (m.shape[2] - 1) + 1}
+    return res, out.cpu().numpy()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -512,6 +538,7 @@ def main():
         "dijkstra_error": dijkstra_error(out),
     }
     line["half"] = bench_half(c, img, m, out, max(3, min(args.steps, 10)))
+    line["toivanen_gpu"], toiv_out = bench_toivanen(c, img, m, 3)
     if not args.no_batched:
         line["converge"] = bench_converge(c)
         line["configs_2d"] = bench_small_configs()
@@ -521,7 +548,7 @@ def main():
     if args.calibrate_copy > 0:
         line["calibration"] = calibrate_copy(args.calibrate_copy)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(c)
+        line["cpu_baseline"] = cpu_baseline(c, toiv_out)
     print(json.dumps(line), flush=True)
 
 

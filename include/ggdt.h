@@ -231,6 +231,29 @@ int ggdt3d_gsf(const float* image, const float* softmask, const float* spacing, 
                float v, float lambda, int iterations, float* out, int C, int D, int H, int W, void* workspace,
                size_t workspace_bytes, hipStream_t stream);
 
+/* ---------------------------------------------- Toivanen's raster scan
+ * The paper's software ships Toivanen's sequential raster scan as the
+ * single-thread comparison method (section "Implementation"); it names the
+ * method without describing it.  Reading: one iteration is a forward sweep over
+ * the voxels in raster order (array order, every axis ascending) and then a
+ * backward sweep in the reverse order; each voxel x in turn takes
+ * min(D(x), D(y) + w(x, y)) over the neighbours y of its 8 (2D) / 26 (3D)
+ * neighbourhood that precede it in the sweep (4 / 13 of them), updating D in
+ * place, with the edge cost and FP32 operation sequence of the passes.  Here
+ * the sweeps run on the GPU by hyperplanes t = 4z + 2y + x (every preceding
+ * neighbour lies on an earlier hyperplane), which gives the sequential sweep's
+ * values bit for bit.  D0 = v * softmask; iterations = 0 writes v * softmask.
+ * Arguments, workspace (ggdt_workspace_min_bytes suffices), aliasing rules and
+ * status codes as ggdt2d / ggdt3d.  One persistent launch for all iterations,
+ * its hyperplanes separated by bounded grid barriers (GGDT_ERR_WATCHDOG via
+ * ggdt_workspace_status if one expires). */
+int ggdt2d_toivanen(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int iterations, float* out, int C, int H, int W, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+int ggdt3d_toivanen(const float* image, const float* softmask, const float* spacing, float v, float lambda,
+                    int iterations, float* out, int C, int D, int H, int W, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
 /* ------------------------------------------------------- no allocation
  * For callers that cannot allocate device memory, not even a workspace (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -74,6 +74,10 @@ _SIGS = {
                             _c_int, _c_int, _vp, _c_size, _vp]),
     "ggdt3d_noalloc": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
                                 _vp]),
+    "ggdt2d_toivanen": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp,
+                                 _c_size, _vp]),
+    "ggdt3d_toivanen": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int, _vp,
+                                 _c_size, _vp]),
     "ggdt2d_half": (_c_int, [_vp, _c_int, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp,
                              _c_size, _vp]),
     "ggdt3d_half": (_c_int, [_vp, _c_int, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int,
@@ -296,6 +300,32 @@ def ggdt_half(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None
     fn = lib.ggdt2d_half if nd == 2 else lib.ggdt3d_half
     rc = fn(_ptr(image), fmt, _ptr(softmask), _spacing(spacing, nd), float(v), float(lamb), int(iterations),
             _ptr(out), C, *spatial, _ptr(workspace), workspace.numel(), _stream())
+    if rc != GGDT_OK:
+        raise GGDTError(rc, fn.__name__)
+    if check:
+        _raise_if_watchdog(workspace, fn.__name__)
+    return out
+
+
+def ggdt_toivanen(image, softmask, spacing, v=1e10, lamb=1.0, iterations=2, out=None, workspace=None, check=False):
+    """Toivanen's raster scan (forward then backward raster sweep per iteration,
+    in place over the preceding half of the 8/26-neighbourhood), run on the GPU by
+    hyperplanes; image ((C,) + spatial or spatial) and softmask (spatial) float32
+    device tensors, 2D or 3D.  check as in ggdt2d."""
+    lib = load_library()
+    image, softmask, spatial = _prep(image, softmask)
+    nd, C = len(spatial), image.shape[0]
+    if out is None:
+        out = torch.empty(spatial, dtype=torch.float32, device=softmask.device)
+    else:
+        _check_out(out, spatial, softmask.device)
+    if workspace is None:
+        workspace = new_workspace(spatial, C, softmask.device, minimal=True)
+    else:
+        _check_workspace(workspace, softmask.device)
+    fn = lib.ggdt2d_toivanen if nd == 2 else lib.ggdt3d_toivanen
+    rc = fn(_ptr(image), _ptr(softmask), _spacing(spacing, nd), float(v), float(lamb), int(iterations), _ptr(out), C,
+            *spatial, _ptr(workspace), workspace.numel(), _stream())
     if rc != GGDT_OK:
         raise GGDTError(rc, fn.__name__)
     if check:

@@ -1,0 +1,29 @@
+// Toivanen's raster scan by hyperplanes t = 4z + 2y + x (toivanen.hip); a 2D
+// image is a volume of one plane (dims = {1, H, W}).
+#pragma once
+
+#include "ggdt_internal.h"
+
+namespace ggdt {
+
+constexpr int kToivThreads = 1024;
+constexpr int kWordToivCounter = 8;  // 64-bit grid-barrier arrival counter in the header (words 8, 9)
+
+struct ToivDesc {
+  const float* image;  // (C, N)
+  float* D;            // (N), holds v * M on entry
+  long long N;
+  int C;
+  int dims[3];
+  float lam;
+  float A[13];     // (float)((1 - lambda) * |off_j|_s^2), the spatial term in double
+  int off[13][3];  // offsets (dz, dy, dx) of the neighbours preceding a voxel in the forward sweep
+  int noff;        // 4 (2D) or 13 (3D)
+  int iterations;
+  int T;           // hyperplanes per sweep: 4 (Z - 1) + 2 (H - 1) + (W - 1) + 1
+};
+
+int toivanen_grid(const ToivDesc& d);
+hipError_t launch_toivanen(const ToivDesc& d, unsigned* words, unsigned long long spin_limit, hipStream_t stream);
+
+}  // namespace ggdt
