@@ -8,6 +8,7 @@
 // the co-resident capacity, which the bounded waits require.
 #include "pass_cell.h"
 #include "pass_device.h"
+#include "grid_sync.h"
 
 namespace ggdt {
 namespace {
@@ -16,32 +17,9 @@ using namespace dev;
 
 // All workgroups of an instance have finished the pass: arrive on the counter
 // and wait until `target` arrivals are seen.  False if the wait was abandoned.
-__device__ bool instance_barrier(unsigned* counter, unsigned target, unsigned* words, unsigned long long limit) {
-  __shared__ int s_ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    unsigned long long polls = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (ld_relaxed(words + kWordAbort) != 0u) {
-        ok = 0;
-        break;
-      }
-      if (++polls > limit) {
-        __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-    s_ok = ok;
-  }
-  __syncthreads();
-  const bool ok = s_ok != 0;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
+__device__ __forceinline__ bool instance_barrier(unsigned* counter, unsigned target, unsigned* words,
+                                                 unsigned long long limit) {
+  return counter_barrier<unsigned>(counter, target, words, limit);
 }
 
 // Batched workgroups have kBatchThreads threads: single-channel 3D instances

@@ -19,46 +19,13 @@
 // hyperplane are spread over the threads of a persistent grid, and the
 // hyperplanes are separated by a grid barrier (a workgroup barrier when the
 // grid is one workgroup).
-#include "pass_device.h"
+#include "grid_sync.h"
 #include "toivanen.h"
 
 namespace ggdt {
 
 namespace {
 using namespace dev;
-
-// Grid barrier on a 64-bit arrival counter (target = number of arrivals
-// expected so far); bounded like every inter-workgroup wait.
-__device__ bool grid_barrier(unsigned long long* ctr, unsigned long long target, unsigned* words,
-                             unsigned long long limit) {
-  __shared__ int s_ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    unsigned long long polls = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if ((++polls & 31u) == 0u) {
-        if (ld_relaxed(words + kWordAbort) != 0u) {
-          ok = 0;
-          break;
-        }
-        if (polls > limit) {
-          __hip_atomic_fetch_or(words + kWordAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    s_ok = ok;
-  }
-  __syncthreads();
-  const bool ok = s_ok != 0;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
-}
 
 __global__ __launch_bounds__(kToivThreads) void toivanen_kernel(ToivDesc d, unsigned* words,
                                                                 unsigned long long limit) {
@@ -100,7 +67,7 @@ __global__ __launch_bounds__(kToivThreads) void toivanen_kernel(ToivDesc d, unsi
           __syncthreads();
         } else {
           target += gridDim.x;
-          if (!grid_barrier(ctr, target, words, limit)) return;
+          if (!counter_barrier<unsigned long long>(ctr, target, words, limit)) return;
         }
       }
     }
