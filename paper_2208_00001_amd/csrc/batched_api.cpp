@@ -40,15 +40,27 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Cost of an instance with w workgroups: planes advanced per workgroup, summed
-// over passes (each workgroup walks ceil(tiles / w) tiles through every plane)
-// plus a per-chunk synchronisation term.
+// Cost of an instance with w workgroups, in units of one strided 3D plane
+// step of one tile: over the passes, planes times the tiles each workgroup
+// walks (ceil(tiles / w)) times the step's weight, plus a per-chunk exchange
+// term; layout changes count per round of K tiles a workgroup moves.  Fitted to
+// per-pass durations in a 64-instance batch on MI355X (1.26 us per strided 3D
+// plane step of a tile and 0.23 us per chunk; 2.45 us per step when the scan
+// axis is the contiguous one; 0.53 us per 2D row step and 3.5 us per chunk;
+// 3.9 us per round of 4 layout tiles).
 double instance_cost(const std::vector<PassDesc>& ps, int w) {
   double c = 0.0;
   for (const PassDesc& d : ps) {
+    if (d.op != kOpPass) {
+      const double tiles = (double)d.Np * ((d.Nq + 63) / 64) * ((d.Na + 63) / 64);
+      c += 3.1 * ceil(tiles / ((double)w * (d.K > 0 ? d.K : 1)));
+      continue;
+    }
     const int tiles = d.ntp * d.ntq;
     const int per = (tiles + w - 1) / w;
-    c += (double)(d.Na - 1) * per + 4.0 * d.nchunk;
+    const bool two_d = d.TP == 1;
+    const double step = two_d ? 0.42 : (d.sa == 1 ? 1.9 : 1.0);
+    c += step * (double)(d.Na - 1) * per + (two_d ? 2.8 : 0.19) * d.nchunk;
   }
   return c;
 }
@@ -150,11 +162,38 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   }
   if (n > cap) return GGDT_ERR_UNSUPPORTED;
 
-  // Pass descriptors (schedule order) per instance, chunk length of the kernel class.
+  // Pass descriptors (schedule order) per instance, chunk length of the kernel
+  // class.  As in the plain forward, the passes along the last axis of a
+  // single-channel volume without records run on scan-major copies of D and
+  // of the image in the workspace: layout changes (descriptors with op !=
+  // kOpPass) move the image there before the first pass and D there and back
+  // around each iteration's last two passes.  Workspace offsets not yet known
+  // are marked kSlotD / kSlotImage and filled in with the layout below.
+  constexpr long long kSlotD = -2, kSlotImage = -3;
   std::vector<std::vector<PassDesc>> passes(n);
+  std::vector<bool> sm(n, false);
   for (int i = 0; i < n; ++i) {
     const ggdt_instance& in = instances[i];
     const int npass = in.iterations * 2 * in.ndim;
+    sm[i] = in.ndim == 3 && in.C == 1 && !in.records && npass > 0 && scan_major_bytes(prs[i]) > 0 &&
+            lds >= (size_t)64 * 65 * 4;  // room for one transpose tile
+    const int D0 = prs[i].dims[0], D1 = prs[i].dims[1], D2 = prs[i].dims[2];
+    auto layout_op = [&](int op, const float* src, long long src_off, float* dst, long long dst_off) {
+      PassDesc L;
+      memset(&L, 0, sizeof L);
+      L.op = op;
+      L.image = src;
+      L.image_off = src_off;
+      L.D = dst;
+      L.d_off = dst_off;
+      L.Np = D0;
+      L.Nq = D1;
+      L.Na = D2;
+      // tiles per round: 4 when the launch's LDS holds 4 tiles of 64 x 65 fp32, else 1
+      L.K = lds >= (size_t)4 * 64 * 65 * 4 ? 4 : 1;
+      passes[i].push_back(L);
+    };
+    if (sm[i]) layout_op(kOpToScanMajor, in.image, -1, nullptr, kSlotImage);
     unsigned base = 0;
     for (int p = 0; p < npass; ++p) {
       PassDesc d;
@@ -168,7 +207,20 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
       }
       d.nchunk = (d.Na - 1 + d.K - 1) / d.K;
       base += (unsigned)d.nchunk + 1u;
+      const int k = p % 6;
+      if (sm[i] && k == 4) layout_op(kOpToScanMajor, in.out, -1, nullptr, kSlotD);
+      if (sm[i] && k >= 4) {
+        // planes (z, y) of the [W][D][H] copies: same tiles, offsets and constants
+        d.sa = D0 * D1;
+        d.sp = D1;
+        d.sq = 1;
+        d.image = nullptr;
+        d.image_off = kSlotImage;
+        d.D = nullptr;
+        d.d_off = kSlotD;
+      }
       passes[i].push_back(d);
+      if (sm[i] && k == 5) layout_op(kOpFromScanMajor, nullptr, kSlotD, in.out, -1);
     }
   }
 
@@ -219,8 +271,19 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     bi.image = in.image;
     bi.nimg = (long long)prs[i].C * prs[i].N;
     off = align_up(off + (size_t)2 * max_cells_of(passes[i]) * 8);
+    long long slot_d = -1, slot_img = -1;
+    if (sm[i]) {
+      slot_d = (long long)off;
+      slot_img = (long long)(off + scan_major_bytes(prs[i]) / 2);
+      off = align_up(off + scan_major_bytes(prs[i]));
+    }
+    auto resolve = [&](long long o) { return o == kSlotD ? slot_d : (o == kSlotImage ? slot_img : o); };
     wg0 += w[i];
-    for (const PassDesc& d : passes[i]) flat.push_back(d);
+    for (PassDesc d : passes[i]) {
+      d.image_off = resolve(d.image_off);
+      d.d_off = resolve(d.d_off);
+      flat.push_back(d);
+    }
     plan->h_insts.push_back(bi);
   }
   plan->grid = wg0;

@@ -89,7 +89,16 @@ struct PassDesc {
   int sqrt_normal;     // min_j A[j] >= 2^-96: the general root may use kModeGeneralN
   int converge;        // convergence mode: skip when done, report changes in kWordChanged
   int img_fmt;         // ImgFmt of `image` (16-bit formats: image points to 2-byte elements)
+  // Batched launches only.  op != kOpPass: instead of a pass, the instance's
+  // workgroups change the layout of the fp32 volume [Np][Nq][Na] at `image`
+  // into `D` (kOpToScanMajor: to [Na][Np][Nq]; kOpFromScanMajor: back).
+  // image_off / d_off >= 0: `image` / `D` are at that byte offset of the
+  // launch's workspace (the instance's scan-major copies).
+  int op;
+  long long image_off;
+  long long d_off;
 };
+enum PassOp : int { kOpPass = 0, kOpToScanMajor = 1, kOpFromScanMajor = 2 };
 
 // Reverse of one forward pass (see backward_device.h).  Geometry fields as in
 // PassDesc; abar is read from a_in and written to a_out; gI accumulates dL/dI.
