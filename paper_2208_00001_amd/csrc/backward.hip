@@ -3,6 +3,7 @@
 #include "backward_cell.h"
 #include "backward_device.h"
 #include "grid_sync.h"
+#include "layout.h"
 
 namespace ggdt {
 namespace {
@@ -82,6 +83,34 @@ __device__ __forceinline__ bool bwd_instance_barrier(unsigned* counter, unsigned
 // tile reverse passes (2D and 3D) with 1024 threads.
 static_assert(kBwdBatchKCell == kCellK, "batched single-channel 3D reverse passes use the cell chunk length");
 
+// A layout change of one of an instance's volumes (BwdDesc::op, K tiles per
+// round) by its G workgroups.
+__device__ __forceinline__ void run_bwd_layout_op(const BwdDesc* gp, unsigned char* ws, float* lds, int wg, int G) {
+  const TransposeShape sh = transpose_shape(gp->op == kOpToScanMajor, gp->Np, gp->Nq, gp->Na);
+  const void* src = gp->lsrc_off >= 0 ? (const void*)(ws + gp->lsrc_off) : gp->lsrc;
+  void* dst = gp->ldst_off >= 0 ? (void*)(ws + gp->ldst_off) : gp->ldst;
+  if (gp->esz == 4) {
+    if (gp->K >= 4)
+      layout_rounds<float, kCellThreads, 4>((const float*)src, (float*)dst, sh, lds, wg, G);
+    else
+      layout_rounds<float, kCellThreads, 1>((const float*)src, (float*)dst, sh, lds, wg, G);
+  } else {
+    uint8_t* bl = reinterpret_cast<uint8_t*>(lds);
+    if (gp->K >= 4)
+      layout_rounds<uint8_t, kCellThreads, 4>((const uint8_t*)src, (uint8_t*)dst, sh, bl, wg, G);
+    else
+      layout_rounds<uint8_t, kCellThreads, 1>((const uint8_t*)src, (uint8_t*)dst, sh, bl, wg, G);
+  }
+}
+
+// The same, out of line: the thread-per-cell reverse pass already needs the
+// registers a 1024-thread workgroup has, and an inlined layout change would
+// make it spill.
+__device__ __attribute__((noinline)) void run_bwd_layout_op_call(const BwdDesc* gp, unsigned char* ws, float* lds,
+                                                                 int wg, int G) {
+  run_bwd_layout_op(gp, ws, lds, wg, G);
+}
+
 template <bool CELL3D>
 __global__ __launch_bounds__(kCellThreads) void batched_bwd_kernel(const BatchInst* __restrict__ insts, int ninst,
                                                                const BwdDesc* __restrict__ passes, unsigned char* ws,
@@ -107,6 +136,14 @@ __global__ __launch_bounds__(kCellThreads) void batched_bwd_kernel(const BatchIn
   const unsigned* cls = reinterpret_cast<const unsigned*>(ws + in.cls_off);
   for (int p = 0; p < in.npass; ++p) {
     const BwdDesc* gp = passes + in.pass0 + p;
+    if (gp->op != kOpPass) {
+      if constexpr (CELL3D)
+        run_bwd_layout_op_call(gp, ws, lds, wg, in.nwg);
+      else
+        run_bwd_layout_op(gp, ws, lds, wg, in.nwg);
+      if (p + 1 < in.npass && !bwd_instance_barrier(ctr, (unsigned)(p + 1) * (unsigned)in.nwg, words, limit)) return;
+      continue;
+    }
     const bool scanc = gp->sa == 1;
     constexpr int NT = kCellThreads;
     bool ok;

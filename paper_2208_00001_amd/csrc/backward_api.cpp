@@ -48,6 +48,8 @@ int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records
   d->epoch_base = epoch_base;
   d->a_in_off = -1;
   d->a_out_off = -1;
+  d->op = kOpPass;
+  d->lsrc_off = d->ldst_off = d->image_off = d->rec_off = d->gi_off = -1;
   return GGDT_OK;
 }
 

@@ -74,6 +74,9 @@ __device__ __forceinline__ bool run_bwd_pass(const BwdDesc* gp, unsigned long lo
   BwdDesc g = *gp;
   if (g.a_in_off >= 0) g.a_in = reinterpret_cast<const float*>(reinterpret_cast<unsigned char*>(words) + g.a_in_off);
   if (g.a_out_off >= 0) g.a_out = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(words) + g.a_out_off);
+  if (g.image_off >= 0) g.image = reinterpret_cast<const float*>(reinterpret_cast<unsigned char*>(words) + g.image_off);
+  if (g.rec_off >= 0) g.rec = reinterpret_cast<const uint8_t*>(reinterpret_cast<unsigned char*>(words) + g.rec_off);
+  if (g.gi_off >= 0) g.gI = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(words) + g.gi_off);
   // global-memory views of the descriptor's arrays
   const gmem<const float> gImage = to_gmem(g.image);
   const gmem<const uint8_t> gRec = to_gmem(g.rec);

@@ -44,80 +44,14 @@ __device__ __forceinline__ bool run_pass_rt(const PassDesc* gp, unsigned long lo
   return run_pass_mode<NDIM, TP, TQ, K, false, kModeGeneral, REC, NT>(gp, xbuf, words, cls, limit, lds, wg, G);
 }
 
-// A layout change of one instance (PassDesc::op), spread over its G workgroups
-// by rounds of KT consecutive 64 x 64 tiles.  Every load of a round is issued
-// before any LDS write (unconditionally, from addresses clamped into the
-// volume; LDS slots of clamped loads are never read back), so a round waits
-// for one memory round trip.
-template <int KT>
-__device__ bool run_layout_rounds(const PassDesc& g, const TransposeShape& sh, float* lds, int wg, int G) {
-  constexpr int NT = kBatchThreads, RPT = kTr / (NT / kTr);  // rows of a tile per thread
-  const int tx = threadIdx.x & (kTr - 1), ty = threadIdx.x / kTr;
-  // tiles are numbered b-major, then tile row, then tile column (fewer than
-  // 2^31: the volume has fewer voxels); a round's tiles are consecutive, so
-  // their coordinates follow from the first one's by counting
-  const int tc = (sh.Cc + kTr - 1) / kTr, tr = (sh.R + kTr - 1) / kTr;
-  const int per_b = tc * tr, total = per_b * sh.B;
-  const gmem<const float> src = to_gmem(g.image);
-  const gmem<float> dst = to_gmem(g.D);
-  for (int id0 = wg * KT; id0 < total; id0 += G * KT) {
-    const int n = total - id0 < KT ? total - id0 : KT;
-    int b[KT], r0[KT], c0[KT];
-    {
-      int bb = id0 / per_b;
-      const int rem = id0 - bb * per_b;
-      int trw = rem / tc, tcl = rem - trw * tc;
-#pragma unroll
-      for (int u = 0; u < KT; ++u) {
-        b[u] = bb;
-        r0[u] = trw * kTr;
-        c0[u] = tcl * kTr;
-        if (++tcl == tc) {
-          tcl = 0;
-          if (++trw == tr) {
-            trw = 0;
-            ++bb;
-          }
-        }
-      }
-    }
-    float v[KT][RPT];
-#pragma unroll
-    for (int u = 0; u < KT; ++u) {
-      const int bu = u < n ? b[u] : b[0];
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = min(r0[u] + ty + k * (NT / kTr), sh.R - 1), c = min(c0[u] + tx, sh.Cc - 1);
-        v[u][k] = src[bu * sh.sbs + (long long)r * sh.srs + c];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < KT; ++u)
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) lds[u * kTrTileElems + (ty + k * (NT / kTr)) * (kTr + 1) + tx] = v[u][k];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < KT; ++u) {
-      if (u >= n) break;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int i = ty + k * (NT / kTr);
-        const int c = c0[u] + i, r = r0[u] + tx;
-        if (r < sh.R && c < sh.Cc)
-          dst[b[u] * sh.dbs + (long long)c * sh.drs + r] = lds[u * kTrTileElems + tx * (kTr + 1) + i];
-      }
-    }
-    __syncthreads();  // the tiles are refilled by the next round
-  }
-  return true;
-}
-
+// A layout change of one instance (PassDesc::op) by its G workgroups;
 // PassDesc::K: tiles per round the launch's LDS holds (4, else 1).
-__device__ bool run_layout_op(const PassDesc* gp, float* lds, int wg, int G) {
-  const PassDesc g = *gp;
+__device__ __forceinline__ bool run_layout_op(const PassDesc* gp, unsigned* words, float* lds, int wg, int G) {
+  const PassDesc g = resolve_offsets(*gp, words);
   const TransposeShape sh = transpose_shape(g.op == kOpToScanMajor, g.Np, g.Nq, g.Na);
-  if (g.K >= 4) return run_layout_rounds<4>(g, sh, lds, wg, G);
-  return run_layout_rounds<1>(g, sh, lds, wg, G);
+  if (g.K >= 4) layout_rounds<float, kBatchThreads, 4>(g.image, g.D, sh, lds, wg, G);
+  else layout_rounds<float, kBatchThreads, 1>(g.image, g.D, sh, lds, wg, G);
+  return true;
 }
 
 // CT: tile side of the thread-per-cell pass for 3D instances (0: the tile pass).
@@ -141,20 +75,11 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(const BatchInst*
   unsigned long long* xbuf = reinterpret_cast<unsigned long long*>(ws + in.xbuf_off);
   unsigned* ctr = reinterpret_cast<unsigned*>(ws + in.ctr_off);
   const unsigned* cls = reinterpret_cast<const unsigned*>(ws + in.cls_off);
-  // The instance's current descriptor, with its workspace offsets resolved.
-  __shared__ PassDesc s_pd;
   for (int p = 0; p < in.npass; ++p) {
-    if (threadIdx.x == 0) {
-      PassDesc t = passes[in.pass0 + p];
-      if (t.image_off >= 0) t.image = reinterpret_cast<const float*>(ws + t.image_off);
-      if (t.d_off >= 0) t.D = reinterpret_cast<float*>(ws + t.d_off);
-      s_pd = t;
-    }
-    __syncthreads();
-    const PassDesc* gp = &s_pd;
+    const PassDesc* gp = passes + in.pass0 + p;
     bool ok;
     if (gp->op != kOpPass) {
-      ok = run_layout_op(gp, lds, wg, in.nwg);
+      ok = run_layout_op(gp, words, lds, wg, in.nwg);
     } else if (in.ndim == 3) {
       if constexpr (CT != 0)
         ok = run_pass_cell_rt<REC, CT, K3>(gp, xbuf, words, cls, in.mode, limit, carve_cell_lds(lds), wg, in.nwg);

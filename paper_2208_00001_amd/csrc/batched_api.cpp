@@ -30,6 +30,7 @@ struct ggdt_plan {
   int bgrid = 0;
   size_t blds = 0;
   size_t fwd_ws = 0;
+  size_t reset_bytes = 0;  // the header, class words, counters and exchange words: cleared by each run
   ggdt::BatchInst* d_binsts = nullptr;
   ggdt::BwdDesc* d_bpasses = nullptr;
 };
@@ -253,6 +254,8 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   off = align_up(off + (size_t)n * 4);
   const size_t ctr_off = off;
   off = align_up(off + (size_t)n * 4);
+  // Exchange words of every instance first (the region each run clears),
+  // then the instances' scan-major copies (never cleared: written before read).
   std::vector<PassDesc> flat;
   int wg0 = 0;
   for (int i = 0; i < n; ++i) {
@@ -262,7 +265,6 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     bi.ndim = in.ndim;
     bi.mode = requested_mode(in.lambda, in.C);
     bi.npass = (int)passes[i].size();
-    bi.pass0 = (int)flat.size();
     bi.wg0 = wg0;
     bi.nwg = w[i];
     bi.xbuf_off = (long long)off;
@@ -271,6 +273,11 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     bi.image = in.image;
     bi.nimg = (long long)prs[i].C * prs[i].N;
     off = align_up(off + (size_t)2 * max_cells_of(passes[i]) * 8);
+    wg0 += w[i];
+    plan->h_insts.push_back(bi);
+  }
+  plan->reset_bytes = off;
+  for (int i = 0; i < n; ++i) {
     long long slot_d = -1, slot_img = -1;
     if (sm[i]) {
       slot_d = (long long)off;
@@ -278,13 +285,12 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
       off = align_up(off + scan_major_bytes(prs[i]));
     }
     auto resolve = [&](long long o) { return o == kSlotD ? slot_d : (o == kSlotImage ? slot_img : o); };
-    wg0 += w[i];
+    plan->h_insts[i].pass0 = (int)flat.size();
     for (PassDesc d : passes[i]) {
       d.image_off = resolve(d.image_off);
       d.d_off = resolve(d.d_off);
       flat.push_back(d);
     }
-    plan->h_insts.push_back(bi);
   }
   plan->grid = wg0;
   plan->nwg = w;
@@ -300,7 +306,9 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   size_t boff = off;
   if (want_bwd) {
     const int bclass = (maxC <= 1 && !has2d) ? 0 : 1;
-    const size_t blds = batched_bwd_lds_bytes(maxC2, maxC3);
+    // (single-channel volumes: room for four tiles of the layout changes)
+    const size_t blds0 = batched_bwd_lds_bytes(maxC2, maxC3), lds4 = (size_t)4 * 64 * 65 * 4;
+    const size_t blds = bclass == 0 && blds0 < lds4 ? lds4 : blds0;
     int bcap = blds <= kMaxLdsBytes ? batched_bwd_capacity(bclass, blds) : 0;
     if (tuning && tuning->wg_per_cu > 0 && bcap > 0) {
       int dev = 0, cus = 0;
@@ -316,10 +324,53 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
         scratch_off[i] = (long long)boff;
         boff = align_up(boff + (size_t)prs[i].N * 4);
       }
+      // As in the forward, the reverses of the passes along the last axis of a
+      // single-channel volume run on scan-major copies: of the image (once),
+      // and per iteration of abar, dL/dI and the two passes' records, moved
+      // there before the pair of reverse passes and abar and dL/dI back after.
+      const size_t per_tile4 = (size_t)64 * 65 * 4, per_tile1 = (size_t)64 * 65;
       for (int i = 0; i < n; ++i) {
         const ggdt_instance& in = instances[i];
         const int P = in.iterations * 2 * in.ndim;
         const int K = in.ndim == 3 ? (bclass == 0 ? kBwdBatchKCell : kBwdBatchK3) : kBwdBatchK2;
+        const bool bsm = bclass == 0 && in.ndim == 3 && in.C == 1 && P > 0 && scan_major_bytes(prs[i]) > 0 &&
+                         blds >= per_tile4;
+        const int D0 = prs[i].dims[0], D1 = prs[i].dims[1], D2 = prs[i].dims[2];
+        const size_t vol4 = align_up((size_t)prs[i].N * 4), vol1 = align_up((size_t)prs[i].N);
+        long long s_img = -1, s_a = -1, s_b = -1, s_g = -1, s_r[2] = {-1, -1};
+        if (bsm) {
+          s_img = (long long)boff;
+          s_a = s_img + (long long)vol4;
+          s_b = s_a + (long long)vol4;
+          s_g = s_b + (long long)vol4;
+          s_r[0] = s_g + (long long)vol4;
+          s_r[1] = s_r[0] + (long long)vol1;
+          boff = (size_t)s_r[1] + vol1;
+        }
+        auto op = [&](int kind, int esz, const void* src, long long src_off, void* dst, long long dst_off) {
+          BwdDesc L;
+          memset(&L, 0, sizeof L);
+          L.op = kind;
+          L.esz = esz;
+          L.lsrc = src;
+          L.lsrc_off = src_off;
+          L.ldst = dst;
+          L.ldst_off = dst_off;
+          L.image_off = L.rec_off = L.gi_off = L.a_in_off = L.a_out_off = -1;
+          L.Np = D0;
+          L.Nq = D1;
+          L.Na = D2;
+          L.K = blds >= 4 * (esz == 4 ? per_tile4 : per_tile1) ? 4 : 1;
+          PassDesc geo{};
+          geo.op = kind;
+          geo.Np = D0;
+          geo.Nq = D1;
+          geo.Na = D2;
+          geo.K = L.K;
+          bgeo[i].push_back(geo);
+          bflat.push_back(L);
+        };
+        if (bsm) op(kOpToScanMajor, 4, in.image, -1, nullptr, s_img);
         unsigned base = 0;
         for (int q = 0; q < P; ++q) {
           const int p = P - 1 - q;
@@ -342,15 +393,45 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
             d.a_in = prev_gm ? in.grad_softmask : nullptr;
             d.a_in_off = prev_gm ? -1 : scratch_off[i];
           }
+          const int k = p % 6;
+          if (bsm && k == 5) {  // first of the pair (2, -), (2, +) in reverse order
+            op(kOpToScanMajor, 4, d.a_in, d.a_in_off, nullptr, s_a);
+            op(kOpToScanMajor, 4, in.grad_image, -1, nullptr, s_g);
+            op(kOpToScanMajor, 1, in.records + (size_t)p * prs[i].N, -1, nullptr, s_r[0]);
+            op(kOpToScanMajor, 1, in.records + (size_t)(p - 1) * prs[i].N, -1, nullptr, s_r[1]);
+          }
+          const float* out_ptr = d.a_out;
+          const long long out_off = d.a_out_off;
+          if (bsm && k >= 4) {
+            // planes (z, y) of the [W][D][H] copies: same tiles, offsets and constants
+            d.sa = D0 * D1;
+            d.sp = D1;
+            d.sq = 1;
+            d.image = nullptr;
+            d.image_off = s_img;
+            d.rec = nullptr;
+            d.rec_off = s_r[k == 5 ? 0 : 1];
+            d.gI = nullptr;
+            d.gi_off = s_g;
+            d.a_in = nullptr;
+            d.a_in_off = k == 5 ? s_a : s_b;
+            d.a_out = nullptr;
+            d.a_out_off = k == 5 ? s_b : s_a;
+          }
           PassDesc geo{};
           geo.TP = d.TP;
           geo.TQ = d.TQ;
           geo.Na = d.Na;
+          geo.sa = d.sa;
           geo.ntp = d.ntp;
           geo.ntq = d.ntq;
           geo.nchunk = d.nchunk;
           bgeo[i].push_back(geo);
           bflat.push_back(d);
+          if (bsm && k == 4) {  // abar and dL/dI back to the array layout
+            op(kOpFromScanMajor, 4, nullptr, s_a, const_cast<float*>(out_ptr), out_off);
+            op(kOpFromScanMajor, 4, nullptr, s_g, in.grad_image, -1);
+          }
         }
       }
       std::vector<int> bw(n, 1);
@@ -412,7 +493,7 @@ int ggdt_batched_run(const ggdt_plan* plan, void* workspace, size_t workspace_by
   if (!plan || !workspace) return GGDT_ERR_NULL_PTR;
   if (workspace_bytes < plan->ws_bytes) return GGDT_ERR_WORKSPACE_TOO_SMALL;
   unsigned char* ws = (unsigned char*)workspace;
-  if (launch_reset((unsigned*)ws, (long long)(plan->ws_bytes / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (launch_reset((unsigned*)ws, (long long)(plan->reset_bytes / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (plan->any_classify && launch_batched_classify(plan->d_insts, plan->n, ws, stream) != hipSuccess)
     return GGDT_ERR_HIP;
   // instances with zero iterations: D = v * M
@@ -435,7 +516,7 @@ int ggdt_batched_backward(const ggdt_plan* plan, void* workspace, size_t workspa
   if (!plan->has_bwd) return GGDT_ERR_UNSUPPORTED;
   if (workspace_bytes < plan->ws_bytes) return GGDT_ERR_WORKSPACE_TOO_SMALL;
   unsigned char* ws = (unsigned char*)workspace;
-  if (launch_reset((unsigned*)ws, (long long)(plan->fwd_ws / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
+  if (launch_reset((unsigned*)ws, (long long)(plan->reset_bytes / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (plan->any_classify && launch_batched_classify(plan->d_insts, plan->n, ws, stream) != hipSuccess)
     return GGDT_ERR_HIP;
   for (int i = 0; i < plan->n; ++i) {

@@ -124,6 +124,16 @@ struct BwdDesc {
   long long a_in_off;   // >= 0: a_in is at this byte offset of the workspace (batched scratch)
   long long a_out_off;  // >= 0: same for a_out
   int sqrt_normal;      // as in PassDesc
+  // Batched launches only (as PassDesc::op).  op != kOpPass: a layout change
+  // of the instance's esz-byte volume [Np][Nq][Na] at lsrc into ldst (K tiles
+  // per round); for passes, image_off / rec_off / gi_off >= 0 place image /
+  // rec / gI at that byte offset of the workspace (lsrc_off / ldst_off the
+  // same for an op's operands).
+  int op;
+  int esz;
+  const void* lsrc;
+  void* ldst;
+  long long lsrc_off, ldst_off, image_off, rec_off, gi_off;
 };
 
 // One instance of a batched launch (device-resident table).  Its passes are

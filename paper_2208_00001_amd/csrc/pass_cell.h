@@ -108,7 +108,7 @@ __device__ __forceinline__ bool run_pass_cell(const PassDesc* gp, unsigned long 
   using Geo = CellGeom<TT, KC>;
   constexpr int TP = Geo::TP, TQ = Geo::TQ, K = Geo::K, BQ = Geo::BQ, NB = Geo::NB;
   constexpr int SC = Geo::SC, SCR = Geo::SCR, STAGE = Geo::STAGE;
-  const PassDesc g = *gp;
+  const PassDesc g = resolve_offsets(*gp, words);
   // global-memory views of the descriptor's arrays (the image in its storage format)
   const gmem<const float> gImage = to_gmem(g.image);           // fp32 image
   const gmem<const uint16_t> gImage16 = image_of<kImgBF16>(g.image);  // 16-bit image (FMT != kImgF32)

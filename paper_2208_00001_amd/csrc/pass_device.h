@@ -125,6 +125,16 @@ __device__ __forceinline__ float general_root(float x) {
   return MODE == kModeGeneralN ? sqrt_rn_normal(x) : sqrtf(x);
 }
 
+// A descriptor whose arrays lie in the workspace (batched launches: the
+// scan-major copies) gives them as byte offsets from the workspace base,
+// `words`; the pointers are filled in here.
+__device__ __forceinline__ PassDesc resolve_offsets(PassDesc g, unsigned* words) {
+  unsigned char* ws = reinterpret_cast<unsigned char*>(words);
+  if (g.image_off >= 0) g.image = reinterpret_cast<const float*>(ws + g.image_off);
+  if (g.d_off >= 0) g.D = reinterpret_cast<float*>(ws + g.d_off);
+  return g;
+}
+
 // Mode for a pass whose requested mode RMODE is the general one: the
 // normal-range root when the spatial terms allow it and no image value is huge.
 __device__ __forceinline__ bool general_n_ok(int sqrt_normal, const unsigned* cls_word) {
@@ -154,7 +164,7 @@ __device__ __forceinline__ float edge_cost(const PassDesc& g, int j, float ix0, 
 template <int NDIM, int TP, int TQ, int K, bool SCANC, int MODE, bool REC, int NT = kThreads>
 __device__ __forceinline__ bool run_pass(const PassDesc* gp, unsigned long long* xbuf, unsigned* words,
                                          unsigned long long limit, float* lds, int wg, int G) {
-  const PassDesc g = *gp;  // uniform copy: no aliasing with the stores below
+  const PassDesc g = resolve_offsets(*gp, words);  // uniform copy: no aliasing with the stores below
   // global-memory views of the descriptor's arrays
   const gmem<const float> gImage = to_gmem(g.image);
   const gmem<const float> gMask = to_gmem(g.mask);
