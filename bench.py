@@ -19,10 +19,18 @@ Also reported (same JSON line):
                 against the MI355X HBM peak (8 TB/s) and against the measured rate
                 of a streaming kernel on 2 GiB; traffic from rocprofv3 counters
                 when a summary for the current kernel source exists
+  dijkstra_error  relative error of the FP32 schedule against exact (FP64 Dijkstra) distances
+                for every workload, from the stored table written by the oracle, after checking
+                that this run's output has the oracle's digest
+  half          the same volume with its image stored as fp16 and as bf16 (10 B per voxel
+                update): time and the change against the fp32 image's result
+  toivanen_gpu  Toivanen's raster scan on the GPU (hyperplane sweeps), one iteration of the
+                same volume; the CPU leg checks its output against the oracle's sweeps
   converge      the same volume run to its fixed point (iterations and time)
   configs_2d    the 128^2 and 2048^2 x 3 images, voxel-updates/s per lambda
+  composed      signed distance and geodesic symmetric filter of the same volume
   cpu_baseline  the CPU oracle (single thread, and OpenMP over each plane) on a bounded sample: one
-                iteration (6 passes) of the same volume
+                iteration (6 passes) of the same volume; Toivanen's scan on one thread
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 """
