@@ -72,8 +72,9 @@ const char* ggdt_strerror(int status);
  * word and the watchdog word; its content need not be initialised by the
  * caller.  For single-channel volumes it also holds copies of D and of the
  * image laid out [W][D][H] (the last axis slowest), on which the passes along
- * the last axis run as strided passes (a library addition; the passes compute
- * the same values).  ggdt_workspace_min_bytes is the smallest size the
+ * the last axis run as strided passes, and room for one such pass's records
+ * before they are moved to the array layout (a library addition; the passes
+ * compute the same values and records).  ggdt_workspace_min_bytes is the smallest size the
  * forward accepts: with less than ggdt_workspace_bytes it runs those passes in
  * place, more slowly.  The two are equal for images and multi-channel
  * volumes. */
@@ -169,10 +170,15 @@ int ggdt_workspace_iterations(const void* workspace, hipStream_t stream, int* it
  * of a loss of D with respect to the image and the soft mask, obtained by
  * running the recorded minimisations of the forward schedule in reverse. */
 
-/* Bytes of device workspace the backward entry points need: the forward's
- * workspace plus one fp32 adjoint buffer of prod(dims) values.  0 for invalid
- * shapes.  1 <= C <= 8 for the backward. */
+/* Bytes of device workspace the backward entry points use: the forward's
+ * minimal workspace plus one fp32 adjoint buffer of prod(dims) values, plus,
+ * for single-channel volumes, scan-major copies (image, two adjoint volumes,
+ * dL/dI, two passes' records) on which the reverses of the passes along the
+ * last axis run as strided passes.  ggdt_backward_workspace_min_bytes is the
+ * smallest size accepted (without the copies those reverse passes run in
+ * place, more slowly).  0 for invalid shapes.  1 <= C <= 8 for the backward. */
 size_t ggdt_backward_workspace_bytes(int ndim, const int* dims, int C);
+size_t ggdt_backward_workspace_min_bytes(int ndim, const int* dims, int C);
 
 /* Backward: exact reverse of the recorded schedule.  Given dL/dD (grad_out) and
  * the records of the forward with the same image, spacing, v, lambda and
@@ -209,8 +215,7 @@ int ggdt3d_backward(const float* image, const uint8_t* records, const float* gra
 
 /* Workspace bytes: the transform's minimal workspace plus 2 (signed) or 4
  * (GSF) fp32 buffers of prod(dims) values, plus, for single-channel volumes,
- * the scan-major copies described at ggdt_workspace_bytes (without them,
- * i.e. with 2 x prod(dims) x 4 bytes less, rounded to 256-byte multiples, the
+ * the scan-major area described at ggdt_workspace_bytes (with less room, the
  * passes along the last axis run in place).  0 for invalid shapes. */
 size_t ggdt_signed_workspace_bytes(int ndim, const int* dims, int C);
 size_t ggdt_gsf_workspace_bytes(int ndim, const int* dims, int C);

@@ -47,6 +47,7 @@ _SIGS = {
     "ggdt_workspace_min_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt_records_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt_backward_workspace_bytes": (_c_size, [_c_int, _vp, _c_int]),
+    "ggdt_backward_workspace_min_bytes": (_c_size, [_c_int, _vp, _c_int]),
     "ggdt2d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _vp, _c_size, _vp]),
     "ggdt3d": (_c_int, [_vp, _vp, _vp, _c_float, _c_float, _c_int, _vp, _c_int, _c_int, _c_int, _c_int, _vp, _c_size,
                         _vp]),
@@ -226,8 +227,7 @@ def _forward(image, softmask, spacing, v, lamb, iterations, out, workspace, reco
     if records is not None:
         _check_records(records, spatial, iterations, softmask.device)
     if workspace is None:
-        # a forward with records keeps every pass in place: no scan-major copies
-        workspace = new_workspace(spatial, C, softmask.device, minimal=records is not None)
+        workspace = new_workspace(spatial, C, softmask.device)
     else:
         _check_workspace(workspace, softmask.device)
     sp = _spacing(spacing, nd)
@@ -465,7 +465,7 @@ class GGDTFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, image, softmask, spacing, v, lamb, iterations):
         _, sm, spatial = _prep(image.detach(), softmask.detach())
-        ws = new_workspace(spatial, 1 if image.dim() == len(spatial) else image.shape[0], sm.device, minimal=True)
+        ws = new_workspace(spatial, 1 if image.dim() == len(spatial) else image.shape[0], sm.device)
         out, rec = ggdt_forward_rec(image.detach(), softmask.detach(), spacing, v, lamb, iterations, workspace=ws)
         ctx.save_for_backward(image.detach(), rec)
         ctx.fwd_workspace = ws

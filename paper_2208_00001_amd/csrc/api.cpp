@@ -208,12 +208,15 @@ size_t workspace_for(const Problem& pr, const Tuning& tu) {
   return (size_t)kHeaderWords * 4 + xbuf;
 }
 
-// Bytes of the scan-major copies (D, then the image, each 256-byte aligned)
+// Bytes of one scan-major fp32 volume, and of the scan-major area of a
+// forward (D, then the image, then one pass's records, each 256-byte aligned)
 // through which the passes along the last axis of a single-channel volume run
 // as strided passes; 0 where the forward keeps those passes in place.
+size_t scan_major_vol_bytes(const Problem& pr) { return ((size_t)pr.N * 4 + 255) / 256 * 256; }
+
 size_t scan_major_bytes(const Problem& pr) {
   if (pr.ndim != 3 || pr.C != 1 || pr.dims[2] < 2) return 0;
-  return 2 * (((size_t)pr.N * 4 + 255) / 256 * 256);
+  return 2 * scan_major_vol_bytes(pr) + ((size_t)pr.N + 255) / 256 * 256;
 }
 
 // The pass along axis 2 on the scan-major copies ([W][D][H]: the scan axis
@@ -273,11 +276,18 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
     d.xbuf = xbuf;
     base += (unsigned)d.nchunk + 1u;
     const int k = p % (2 * pr.ndim);
-    if (sm.on && k >= 4) use_scan_major(pr, sm.image, sm.D, &d);
+    uint8_t* rec_c = d.rec;  // this pass's records in the array layout
+    if (sm.on && k >= 4) {
+      use_scan_major(pr, sm.image, sm.D, &d);
+      if (rec_c) d.rec = sm.rec;  // written scan-major, moved to the array layout below
+    }
     if (sm.on && k == 4 &&
         launch_to_scan_major(out, sm.D, 4, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) != hipSuccess)
       return GGDT_ERR_HIP;
     if (launch_pass_profiled(d, pr.ndim, words, stream) != hipSuccess) return GGDT_ERR_HIP;
+    if (sm.on && k >= 4 && rec_c &&
+        launch_from_scan_major(sm.rec, rec_c, 1, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) != hipSuccess)
+      return GGDT_ERR_HIP;
     if (sm.on && k == 5 &&
         launch_from_scan_major(sm.D, out, 4, pr.dims[0], pr.dims[1], pr.dims[2], nullptr, stream) != hipSuccess)
       return GGDT_ERR_HIP;
@@ -288,12 +298,12 @@ int enqueue_forward(const Problem& pr, const float* image, const float* mask, co
 
 ScanMajor scan_major_for(const Problem& pr, const uint8_t* records, void* buf) {
   ScanMajor sm{};
-  // Records are stored per voxel in C order, so a forward with records keeps
-  // every pass in place.
-  if (!buf || records || scan_major_bytes(pr) == 0) return sm;
+  (void)records;  // records of scan-major passes are staged and moved to the array layout
+  if (!buf || scan_major_bytes(pr) == 0) return sm;
   sm.on = true;
   sm.D = static_cast<float*>(buf);
-  sm.image = static_cast<unsigned char*>(buf) + scan_major_bytes(pr) / 2;
+  sm.image = static_cast<unsigned char*>(buf) + scan_major_vol_bytes(pr);
+  sm.rec = static_cast<uint8_t*>(buf) + 2 * scan_major_vol_bytes(pr);
   return sm;
 }
 

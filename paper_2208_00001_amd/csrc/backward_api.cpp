@@ -16,6 +16,13 @@ size_t bwd_workspace_for(const Problem& pr) {
   return base + ((size_t)pr.N * 4 + 255) / 256 * 256;
 }
 
+// The scan-major area of the reverse (after bwd_workspace_for): the image,
+// abar twice, dL/dI (fp32 volumes) and two passes' records (byte volumes).
+size_t bwd_scan_major_bytes(const Problem& pr) {
+  if (pr.ndim != 3 || pr.C != 1 || pr.dims[2] < 2) return 0;
+  return 4 * scan_major_vol_bytes(pr) + 2 * (((size_t)pr.N + 255) / 256 * 256);
+}
+
 // Descriptor of the reverse of forward pass p; a_in / a_out / xbuf set by the caller.
 int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,
                    float* gI, int p, int K, unsigned epoch_base, BwdDesc* d) {
@@ -85,14 +92,36 @@ int backward_entry(int ndim, const int* dims, int C, const float* image, const u
   if (iterations == 0) return launch_scale(grad_out, v, grad_softmask, pr.N, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
   if (launch_classify(image, (long long)C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   const int P = iterations * 2 * ndim;
+  // Scan-major copies (as in the forward): the reverses of the passes along
+  // the last axis of a single-channel volume run on [W][D][H] copies of the
+  // image (moved once), of abar and dL/dI (moved there before each pair of
+  // those reverse passes and back after it) and of the pair's records.
+  const size_t smb = bwd_scan_major_bytes(pr), bmin = bwd_workspace_for(pr);
+  const bool sm = smb > 0 && wsb >= bmin + smb;
+  const int D0 = pr.dims[0], D1 = pr.dims[1], D2 = pr.dims[ndim - 1];
+  float *s_img = nullptr, *s_a = nullptr, *s_b = nullptr, *s_g = nullptr;
+  uint8_t* s_r[2] = {nullptr, nullptr};
+  if (sm) {
+    unsigned char* base_p = (unsigned char*)ws + bmin;
+    const size_t vol = scan_major_vol_bytes(pr), vol1 = ((size_t)pr.N + 255) / 256 * 256;
+    s_img = (float*)base_p;
+    s_a = (float*)(base_p + vol);
+    s_b = (float*)(base_p + 2 * vol);
+    s_g = (float*)(base_p + 3 * vol);
+    s_r[0] = base_p + 4 * vol;
+    s_r[1] = base_p + 4 * vol + vol1;
+    if (launch_to_scan_major(image, s_img, 4, D0, D1, D2, nullptr, stream) != hipSuccess) return GGDT_ERR_HIP;
+  }
   unsigned base = 0;
   const float* a_in = grad_out;
   for (int q = 0; q < P; ++q) {
     const int p = P - 1 - q;
+    const int k = p % (2 * ndim);
+    const bool on_copy = sm && k >= 4;
     BwdDesc d;
     PassDesc g;
     pass_geometry(pr, (p % (2 * ndim)) / 2, &g);
-    const int K = bwd_chunk_for(ndim, C, g.sa == 1);
+    const int K = bwd_chunk_for(ndim, C, g.sa == 1 && !on_copy);
     if (K <= 0) return GGDT_ERR_UNSUPPORTED;
     if ((rc = build_bwd_pass(pr, image, records, spacing, lam, grad_image, p, K, base, &d))) return rc;
     float* a_out = ((P - 1 - q) % 2 == 0) ? grad_softmask : scratch;
@@ -100,10 +129,34 @@ int backward_entry(int ndim, const int* dims, int C, const float* image, const u
     d.a_out = a_out;
     d.xbuf = xbuf;
     base += (unsigned)d.nchunk + 1u;
+    if (sm && k == 5) {  // first of the pair (2, -), (2, +) in reverse order
+      if (launch_to_scan_major(a_in, s_a, 4, D0, D1, D2, nullptr, stream) != hipSuccess ||
+          launch_to_scan_major(grad_image, s_g, 4, D0, D1, D2, nullptr, stream) != hipSuccess ||
+          launch_to_scan_major(records + (size_t)p * pr.N, s_r[0], 1, D0, D1, D2, nullptr, stream) != hipSuccess ||
+          launch_to_scan_major(records + (size_t)(p - 1) * pr.N, s_r[1], 1, D0, D1, D2, nullptr, stream) !=
+              hipSuccess)
+        return GGDT_ERR_HIP;
+    }
+    if (on_copy) {
+      // planes (z, y) of the [W][D][H] copies: same tiles, offsets and constants
+      d.sa = D0 * D1;
+      d.sp = D1;
+      d.sq = 1;
+      d.image = s_img;
+      d.rec = s_r[k == 5 ? 0 : 1];
+      d.gI = s_g;
+      d.a_in = k == 5 ? s_a : s_b;
+      d.a_out = k == 5 ? s_b : s_a;
+    }
     prof_before(stream);
     const hipError_t e = launch_bwd_pass(d, ndim, words, g_spin_limit, stream);
     prof_after(stream);
     if (e != hipSuccess) return GGDT_ERR_HIP;
+    if (sm && k == 4) {  // abar and dL/dI back to the array layout
+      if (launch_from_scan_major(s_a, a_out, 4, D0, D1, D2, nullptr, stream) != hipSuccess ||
+          launch_from_scan_major(s_g, grad_image, 4, D0, D1, D2, nullptr, stream) != hipSuccess)
+        return GGDT_ERR_HIP;
+    }
     a_in = a_out;
   }
   // the last reversed pass wrote grad_softmask: dL/dM = v * abar
@@ -118,6 +171,13 @@ using namespace ggdt;
 extern "C" {
 
 size_t ggdt_backward_workspace_bytes(int ndim, const int* dims, int C) {
+  if (!dims) return 0;
+  Problem pr;
+  if (make_problem(ndim, dims, C, &pr) || C > kMaxBwdChannels) return 0;
+  return bwd_workspace_for(pr) + bwd_scan_major_bytes(pr);
+}
+
+size_t ggdt_backward_workspace_min_bytes(int ndim, const int* dims, int C) {
   if (!dims) return 0;
   Problem pr;
   if (make_problem(ndim, dims, C, &pr) || C > kMaxBwdChannels) return 0;

@@ -281,8 +281,8 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
     long long slot_d = -1, slot_img = -1;
     if (sm[i]) {
       slot_d = (long long)off;
-      slot_img = (long long)(off + scan_major_bytes(prs[i]) / 2);
-      off = align_up(off + scan_major_bytes(prs[i]));
+      slot_img = (long long)(off + scan_major_vol_bytes(prs[i]));
+      off = align_up(off + 2 * scan_major_vol_bytes(prs[i]));
     }
     auto resolve = [&](long long o) { return o == kSlotD ? slot_d : (o == kSlotImage ? slot_img : o); };
     plan->h_insts[i].pass0 = (int)flat.size();

@@ -58,10 +58,12 @@ size_t workspace_for(const Problem& pr, const Tuning& tu);
 // Scan-major copies of D and of the image for the passes along the last axis
 // of a single-channel volume (see layout.hip).
 size_t scan_major_bytes(const Problem& pr);
+size_t scan_major_vol_bytes(const Problem& pr);  // one fp32 volume, 256-byte aligned
 struct ScanMajor {
   bool on;
-  float* D;     // D laid out [W][D][H]
-  void* image;  // the image in its storage format, laid out [W][D][H]
+  float* D;      // D laid out [W][D][H]
+  void* image;   // the image in its storage format, laid out [W][D][H]
+  uint8_t* rec;  // one pass's records laid out [W][D][H] (forward with records)
 };
 // The copies in `buf` (scan_major_bytes(pr) bytes), if the schedule uses them.
 ScanMajor scan_major_for(const Problem& pr, const uint8_t* records, void* buf);

@@ -203,7 +203,7 @@ hipError_t launch_reset(unsigned* ws, long long nwords, hipStream_t stream);
 hipError_t launch_classify(const float* image, long long n, unsigned* words, hipStream_t stream,
                            int img_fmt = kImgF32);
 hipError_t launch_scale(const float* mask, float v, float* out, long long n, hipStream_t stream);
-// Layout changes of a [D0][D1][D2] volume of 4- or 2-byte elements (layout.hip):
+// Layout changes of a [D0][D1][D2] volume of 4-, 2- or 1-byte elements (layout.hip):
 // to [D2][D0][D1] and back.  With `skip` non-null, a launch finding *skip != 0
 // does nothing.
 hipError_t launch_to_scan_major(const void* src, void* dst, int elem_bytes, int D0, int D1, int D2,

@@ -47,6 +47,7 @@ hipError_t launch_layout(bool to_scan_major, const void* src, void* dst, int ele
   const TransposeShape sh = transpose_shape(to_scan_major, D0, D1, D2);
   if (elem_bytes == 4) return launch_t<float>(src, dst, sh, skip, stream);
   if (elem_bytes == 2) return launch_t<uint16_t>(src, dst, sh, skip, stream);
+  if (elem_bytes == 1) return launch_t<uint8_t>(src, dst, sh, skip, stream);
   return hipErrorInvalidValue;
 }
 

@@ -42,6 +42,34 @@ def test_backward_matches_oracle_f32(shape, C, lam, it):
     assert assert_parity(gi.reshape(rgi.shape), rgi, what="dL/dI"), "dL/dI not bitwise"
 
 
+@pytest.mark.parametrize("shape,lam,it", [((23, 31, 19), 0.7, 2), ((9, 40, 66), 1.0, 1), ((30, 21, 130), 0.4, 2)],
+                         ids=lambda v: str(v))
+def test_records_and_backward_scan_major_and_in_place(shape, lam, it):
+    """Single-channel volumes: the forward with records and the backward with
+    their full workspaces (the last-axis passes and their reverses on
+    scan-major copies, records moved to the array layout) and with the minimal
+    ones (in place) both give the oracle's records and gradients bit for bit."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=1, seed=720 + sum(shape), lam=lam, iterations=it, soft=True, v=10.0)
+    W = np.random.default_rng(721).standard_normal(shape).astype(np.float32)
+    ref, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], lam, it, "f32", records=True)
+    rgi, rgm = oracle.backward(c["image"], ref_rec, W, c["spacing"], c["v"], lam, it, "f32")
+    img, m = to_dev(c["image"]), to_dev(c["mask"])
+    nd = (3 * __import__("ctypes").c_int)(*shape)
+    lib = B.load_library()
+    assert lib.ggdt_backward_workspace_bytes(3, nd, 1) > lib.ggdt_backward_workspace_min_bytes(3, nd, 1)
+    for minimal in (False, True):
+        print(f"case {shape} lam={lam} it={it} minimal={minimal}", flush=True)
+        ws = B.new_workspace(shape, 1, img.device, minimal=minimal)
+        out, rec = B.ggdt_forward_rec(img, m, c["spacing"], c["v"], lam, it, workspace=ws, check=True)
+        nb = (lib.ggdt_backward_workspace_min_bytes if minimal else lib.ggdt_backward_workspace_bytes)(3, nd, 1)
+        bws = torch.empty(int(nb), dtype=torch.uint8, device=img.device)
+        gi, gm = B.ggdt_backward(img, rec, to_dev(W), c["spacing"], c["v"], lam, it, workspace=bws, check=True)
+        assert np.array_equal(to_host(out), ref) and np.array_equal(to_host(rec), ref_rec), f"minimal={minimal}"
+        assert assert_parity(to_host(gm), rgm, what="dL/dM"), f"dL/dM not bitwise, minimal={minimal}"
+        assert assert_parity(to_host(gi).reshape(rgi.shape), rgi, what="dL/dI"), f"dL/dI not bitwise, minimal={minimal}"
+
+
 def test_autograd_function():
     from paper_2208_00001_amd.binding import GGDTFunction
     c = synth.small_case((20, 24, 22), C=1, seed=702, lam=0.7, iterations=2, soft=True, v=10.0)
