@@ -338,7 +338,8 @@ int build_pass(const Problem& pr, const float* image, const float* mask, const f
   d->epoch_base = epoch_base;
   d->sqrt_normal = sqrt_normal_for(d->A, pr.ndim);
   d->op = kOpPass;
-  d->image_off = d->d_off = -1;
+  d->esz = 4;
+  d->image_off = d->d_off = d->rec_off = -1;
   return GGDT_OK;
 }
 

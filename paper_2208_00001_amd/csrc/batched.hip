@@ -49,8 +49,17 @@ __device__ __forceinline__ bool run_pass_rt(const PassDesc* gp, unsigned long lo
 __device__ __forceinline__ bool run_layout_op(const PassDesc* gp, unsigned* words, float* lds, int wg, int G) {
   const PassDesc g = resolve_offsets(*gp, words);
   const TransposeShape sh = transpose_shape(g.op == kOpToScanMajor, g.Np, g.Nq, g.Na);
-  if (g.K >= 4) layout_rounds<float, kBatchThreads, 4>(g.image, g.D, sh, lds, wg, G);
-  else layout_rounds<float, kBatchThreads, 1>(g.image, g.D, sh, lds, wg, G);
+  if (g.esz == 1) {  // records (byte volumes)
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(g.image);
+    uint8_t* dst = reinterpret_cast<uint8_t*>(g.D);
+    uint8_t* tiles = reinterpret_cast<uint8_t*>(lds);
+    if (g.K >= 4) layout_rounds<uint8_t, kBatchThreads, 4>(src, dst, sh, tiles, wg, G);
+    else layout_rounds<uint8_t, kBatchThreads, 1>(src, dst, sh, tiles, wg, G);
+  } else if (g.K >= 4) {
+    layout_rounds<float, kBatchThreads, 4>(g.image, g.D, sh, lds, wg, G);
+  } else {
+    layout_rounds<float, kBatchThreads, 1>(g.image, g.D, sh, lds, wg, G);
+  }
   return true;
 }
 

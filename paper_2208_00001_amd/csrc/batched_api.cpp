@@ -170,28 +170,30 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   // kOpPass) move the image there before the first pass and D there and back
   // around each iteration's last two passes.  Workspace offsets not yet known
   // are marked kSlotD / kSlotImage and filled in with the layout below.
-  constexpr long long kSlotD = -2, kSlotImage = -3;
+  constexpr long long kSlotD = -2, kSlotImage = -3, kSlotRec = -4;
   std::vector<std::vector<PassDesc>> passes(n);
   std::vector<bool> sm(n, false);
   for (int i = 0; i < n; ++i) {
     const ggdt_instance& in = instances[i];
     const int npass = in.iterations * 2 * in.ndim;
-    sm[i] = in.ndim == 3 && in.C == 1 && !in.records && npass > 0 && scan_major_bytes(prs[i]) > 0 &&
+    sm[i] = in.ndim == 3 && in.C == 1 && npass > 0 && scan_major_bytes(prs[i]) > 0 &&
             lds >= (size_t)64 * 65 * 4;  // room for one transpose tile
     const int D0 = prs[i].dims[0], D1 = prs[i].dims[1], D2 = prs[i].dims[2];
-    auto layout_op = [&](int op, const float* src, long long src_off, float* dst, long long dst_off) {
+    auto layout_op = [&](int op, const void* src, long long src_off, void* dst, long long dst_off, int esz = 4) {
       PassDesc L;
       memset(&L, 0, sizeof L);
       L.op = op;
-      L.image = src;
+      L.esz = esz;
+      L.rec_off = -1;
+      L.image = static_cast<const float*>(src);
       L.image_off = src_off;
-      L.D = dst;
+      L.D = static_cast<float*>(dst);
       L.d_off = dst_off;
       L.Np = D0;
       L.Nq = D1;
       L.Na = D2;
-      // tiles per round: 4 when the launch's LDS holds 4 tiles of 64 x 65 fp32, else 1
-      L.K = lds >= (size_t)4 * 64 * 65 * 4 ? 4 : 1;
+      // tiles per round: 4 when the launch's LDS holds 4 tiles of 64 x 65 elements, else 1
+      L.K = lds >= (size_t)4 * 64 * 65 * esz ? 4 : 1;
       passes[i].push_back(L);
     };
     if (sm[i]) layout_op(kOpToScanMajor, in.image, -1, nullptr, kSlotImage);
@@ -210,6 +212,7 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
       base += (unsigned)d.nchunk + 1u;
       const int k = p % 6;
       if (sm[i] && k == 4) layout_op(kOpToScanMajor, in.out, -1, nullptr, kSlotD);
+      uint8_t* rec_c = d.rec;  // this pass's records in the array layout
       if (sm[i] && k >= 4) {
         // planes (z, y) of the [W][D][H] copies: same tiles, offsets and constants
         d.sa = D0 * D1;
@@ -219,8 +222,13 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
         d.image_off = kSlotImage;
         d.D = nullptr;
         d.d_off = kSlotD;
+        if (rec_c) {  // staged scan-major, then moved to the array layout
+          d.rec = nullptr;
+          d.rec_off = kSlotRec;
+        }
       }
       passes[i].push_back(d);
+      if (sm[i] && k >= 4 && rec_c) layout_op(kOpFromScanMajor, nullptr, kSlotRec, rec_c, -1, 1);
       if (sm[i] && k == 5) layout_op(kOpFromScanMajor, nullptr, kSlotD, in.out, -1);
     }
   }
@@ -278,17 +286,24 @@ int ggdt_batched_plan(const ggdt_instance* instances, int n, const ggdt_tuning* 
   }
   plan->reset_bytes = off;
   for (int i = 0; i < n; ++i) {
-    long long slot_d = -1, slot_img = -1;
+    long long slot_d = -1, slot_img = -1, slot_rec = -1;
     if (sm[i]) {
       slot_d = (long long)off;
       slot_img = (long long)(off + scan_major_vol_bytes(prs[i]));
       off = align_up(off + 2 * scan_major_vol_bytes(prs[i]));
+      if (instances[i].records) {
+        slot_rec = (long long)off;
+        off = align_up(off + (size_t)prs[i].N);
+      }
     }
-    auto resolve = [&](long long o) { return o == kSlotD ? slot_d : (o == kSlotImage ? slot_img : o); };
+    auto resolve = [&](long long o) {
+      return o == kSlotD ? slot_d : (o == kSlotImage ? slot_img : (o == kSlotRec ? slot_rec : o));
+    };
     plan->h_insts[i].pass0 = (int)flat.size();
     for (PassDesc d : passes[i]) {
       d.image_off = resolve(d.image_off);
       d.d_off = resolve(d.d_off);
+      d.rec_off = resolve(d.rec_off);
       flat.push_back(d);
     }
   }

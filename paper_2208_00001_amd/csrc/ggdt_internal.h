@@ -90,13 +90,16 @@ struct PassDesc {
   int converge;        // convergence mode: skip when done, report changes in kWordChanged
   int img_fmt;         // ImgFmt of `image` (16-bit formats: image points to 2-byte elements)
   // Batched launches only.  op != kOpPass: instead of a pass, the instance's
-  // workgroups change the layout of the fp32 volume [Np][Nq][Na] at `image`
-  // into `D` (kOpToScanMajor: to [Na][Np][Nq]; kOpFromScanMajor: back).
-  // image_off / d_off >= 0: `image` / `D` are at that byte offset of the
-  // launch's workspace (the instance's scan-major copies).
+  // workgroups change the layout of the esz-byte volume [Np][Nq][Na] at
+  // `image` into `D` (kOpToScanMajor: to [Na][Np][Nq]; kOpFromScanMajor:
+  // back).  image_off / d_off / rec_off >= 0: `image` / `D` / `rec` are at
+  // that byte offset of the launch's workspace (the instance's scan-major
+  // copies and records staging).
   int op;
+  int esz;
   long long image_off;
   long long d_off;
+  long long rec_off;
 };
 enum PassOp : int { kOpPass = 0, kOpToScanMajor = 1, kOpFromScanMajor = 2 };
 

@@ -132,6 +132,7 @@ __device__ __forceinline__ PassDesc resolve_offsets(PassDesc g, unsigned* words)
   unsigned char* ws = reinterpret_cast<unsigned char*>(words);
   if (g.image_off >= 0) g.image = reinterpret_cast<const float*>(ws + g.image_off);
   if (g.d_off >= 0) g.D = reinterpret_cast<float*>(ws + g.d_off);
+  if (g.rec_off >= 0) g.rec = reinterpret_cast<uint8_t*>(ws + g.rec_off);
   return g;
 }
 
