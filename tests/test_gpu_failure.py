@@ -77,6 +77,29 @@ def test_watchdog_reported_for_batched_launch(tiny_spin_limit):
     plan.close()
 
 
+def test_watchdog_reported_for_toivanen_grid(tiny_spin_limit):
+    """Toivanen's scan on a multi-workgroup grid: its grid barriers between
+    hyperplanes are bounded like every other wait."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case((80, 81, 20), C=1, seed=930, lam=1.0, iterations=1)  # 6480 rows: several workgroups
+    img, m = to_dev(c["image"]), to_dev(c["mask"])
+    ws = B.new_workspace(c["mask"].shape, 1, img.device, minimal=True)
+    fired = 0
+    for attempt in range(3):
+        print(f"attempt {attempt}: Toivanen with a spin limit of 1 poll", flush=True)
+        try:
+            B.ggdt_toivanen(img, m, c["spacing"], c["v"], c["lam"], 1, workspace=ws, check=True)
+        except B.GGDTError as e:
+            assert e.code == GGDT_ERR_WATCHDOG, e
+            fired += 1
+            break
+    assert fired, "no grid barrier gave up with a spin limit of one poll"
+    B.set_spin_limit(0)
+    out = B.ggdt_toivanen(img, m, c["spacing"], c["v"], c["lam"], 1, workspace=ws, check=True)
+    ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
+    assert np.array_equal(to_host(out), ref)
+
+
 def test_binding_rejects_wrong_buffers():
     from paper_2208_00001_amd import binding as B
     c = synth.small_case((8, 9, 10), C=1, seed=920, lam=0.7, iterations=1)
