@@ -67,3 +67,22 @@ def test_half_unsupported_geometries_are_rejected():
     with pytest.raises(B.GGDTError) as e:
         B.ggdt_half(img, m, (1.0, 1.0, 1.0), 1e10, 1.0, 1)
     assert e.value.code == GGDT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("fmt", list(DTYPES))
+@pytest.mark.parametrize("shape,lam,it", [((24, 16, 64), 1.0, 2), ((20, 18, 50), 0.6, 2), ((13, 11, 37), 0.0, 2),
+                                          ((9, 40, 72), 0.8, 1)], ids=lambda v: str(v))
+def test_half_volume_last_axis_in_place(fmt, shape, lam, it):
+    """Single-channel volumes with the minimal workspace: the passes along the
+    last axis stage the 16-bit image in place, by 16-byte groups of 8 positions
+    (every run start 16-byte aligned), by 4-byte pairs (even offsets) or per
+    lane (odd), and must still equal the oracle on the widened image."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=1, seed=980 + sum(shape), lam=lam, iterations=it)
+    print(f"case {c['name']} {fmt} lam={lam} it={it} (minimal workspace)", flush=True)
+    img16, widened = rounded(c["image"], DTYPES[fmt])
+    ws = B.new_workspace(shape, 1, "cuda", minimal=True)
+    got = to_host(B.ggdt_half(img16.to("cuda"), to_dev(c["mask"]), c["spacing"], c["v"], lam, it, workspace=ws,
+                              check=True))
+    ref = oracle.ggdt(widened, c["mask"], c["spacing"], c["v"], lam, it, "f32")
+    assert assert_parity(got, ref, what=f"{fmt} {c['name']}"), "not bitwise"
