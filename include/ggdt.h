@@ -249,9 +249,11 @@ int ggdt3d_gsf(const float* image, const float* softmask, const float* spacing, 
  * neighbour lies on an earlier hyperplane), which gives the sequential sweep's
  * values bit for bit.  D0 = v * softmask; iterations = 0 writes v * softmask.
  * Arguments, workspace (ggdt_workspace_min_bytes suffices), aliasing rules and
- * status codes as ggdt2d / ggdt3d.  One persistent launch for all iterations,
- * its hyperplanes separated by bounded grid barriers (GGDT_ERR_WATCHDOG via
- * ggdt_workspace_status if one expires). */
+ * status codes as ggdt2d / ggdt3d.  One persistent launch for all iterations:
+ * row blocks (slabs of whole planes of a volume, bands of image rows) run as a
+ * pipeline, each waiting, bounded, for its one neighbour's progress
+ * (GGDT_ERR_WATCHDOG via ggdt_workspace_status if a wait expires); returns
+ * GGDT_ERR_UNSUPPORTED if the blocks cannot all be co-resident. */
 int ggdt2d_toivanen(const float* image, const float* softmask, const float* spacing, float v, float lambda,
                     int iterations, float* out, int C, int H, int W, void* workspace, size_t workspace_bytes,
                     hipStream_t stream);

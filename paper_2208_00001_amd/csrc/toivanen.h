@@ -6,8 +6,7 @@
 
 namespace ggdt {
 
-constexpr int kToivThreads = 1024;
-constexpr int kWordToivCounter = 8;  // 64-bit grid-barrier arrival counter in the header (words 8, 9)
+constexpr int kToivThreads = 1024;  // threads per workgroup: one row (z, y) each per step
 
 struct ToivDesc {
   const float* image;  // (C, N)
@@ -21,9 +20,16 @@ struct ToivDesc {
   int noff;        // 4 (2D) or 13 (3D)
   int iterations;
   int T;           // hyperplanes per sweep: 4 (Z - 1) + 2 (H - 1) + (W - 1) + 1
+  // Row blocks, one workgroup each: slabs of `bz` planes (all rows y) of a
+  // volume, or bands of `by` rows of an image (Z = 1, bz = 1); `nb` blocks.
+  int bz, by, nb;
+  int publish;  // steps between progress publications
 };
 
-int toivanen_grid(const ToivDesc& d);
+// Pick the row blocks of a problem (at most `cap` of them, one workgroup each,
+// and at most `words` progress words); false if none fits.
+bool toivanen_blocks(ToivDesc* d, int cap, long long words);
+int toivanen_capacity();
 hipError_t launch_toivanen(const ToivDesc& d, unsigned* words, unsigned long long spin_limit, hipStream_t stream);
 
 }  // namespace ggdt

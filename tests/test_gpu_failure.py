@@ -78,10 +78,10 @@ def test_watchdog_reported_for_batched_launch(tiny_spin_limit):
 
 
 def test_watchdog_reported_for_toivanen_grid(tiny_spin_limit):
-    """Toivanen's scan on a multi-workgroup grid: its grid barriers between
-    hyperplanes are bounded like every other wait."""
+    """Toivanen's scan on a pipeline of several row blocks: the waits for the
+    neighbouring block's progress are bounded like every other wait."""
     from paper_2208_00001_amd import binding as B
-    c = synth.small_case((80, 81, 20), C=1, seed=930, lam=1.0, iterations=1)  # 6480 rows: several workgroups
+    c = synth.small_case((80, 81, 20), C=1, seed=930, lam=1.0, iterations=1)  # 7 slabs of 12 planes
     img, m = to_dev(c["image"]), to_dev(c["mask"])
     ws = B.new_workspace(c["mask"].shape, 1, img.device, minimal=True)
     fired = 0
@@ -93,7 +93,7 @@ def test_watchdog_reported_for_toivanen_grid(tiny_spin_limit):
             assert e.code == GGDT_ERR_WATCHDOG, e
             fired += 1
             break
-    assert fired, "no grid barrier gave up with a spin limit of one poll"
+    assert fired, "no wait gave up with a spin limit of one poll"
     B.set_spin_limit(0)
     out = B.ggdt_toivanen(img, m, c["spacing"], c["v"], c["lam"], 1, workspace=ws, check=True)
     ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")

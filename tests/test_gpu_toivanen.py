@@ -1,8 +1,8 @@
 """Toivanen's raster scan on the GPU (hyperplane sweeps) against the oracle's
 sequential FP32 sweeps, bit for bit: 2D and 3D, 1-3 channels, lambda 0, general
-and 1, soft and hard seeds, unit dimensions, iterations 0-3, a one-workgroup
-grid (at most 4096 rows) and multi-workgroup grids with grid barriers between
-hyperplanes, up to the 256^3 benchmark volume (one iteration)."""
+and 1, soft and hard seeds, unit dimensions, iterations 0-3, one row block and
+pipelines of several (ragged) row blocks (bands of 1024 image rows, slabs of
+1024 / H volume planes), up to the 256^3 benchmark volume (one iteration)."""
 import numpy as np
 import pytest
 
@@ -15,8 +15,10 @@ pytestmark = pytest.mark.gpu
 CASES = [
     ((37, 53), 1, 1.0, 2, False), ((64, 65), 3, 0.5, 1, True), ((1, 300), 1, 0.0, 2, False), ((300, 1), 2, 0.8, 1, True),
     ((5, 6, 7), 1, 1.0, 2, False), ((1, 1, 1), 1, 0.5, 1, False), ((9, 1, 30), 1, 0.0, 3, True),
-    ((20, 33, 18), 2, 0.4, 2, True), ((80, 81, 20), 1, 1.0, 2, False),  # 6480 rows: grid barriers
+    ((20, 33, 18), 2, 0.4, 2, True), ((80, 81, 20), 1, 1.0, 2, False),  # 7 slabs of 12 planes
     ((70, 75, 9), 3, 0.7, 1, True), ((33, 40, 12), 1, 0.3, 0, True),
+    ((2100, 37), 2, 0.6, 2, True), ((1030, 5), 1, 1.0, 1, False),  # 3 and 2 bands of image rows
+    ((3, 1500, 4), 1, 0.9, 2, False), ((300, 16, 3), 1, 0.5, 2, True),  # slabs of 1 plane; 5 ragged slabs
 ]
 
 
