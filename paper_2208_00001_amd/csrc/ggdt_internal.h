@@ -17,6 +17,7 @@ constexpr int kWordClass = 1;   // image classification bits, see below
 constexpr int kWordChanged = 2;
 constexpr int kWordDone = 3;
 constexpr int kWordIters = 4;
+constexpr int kWordSink = 5;    // written by idle lanes to keep a kernel's stores unconditional; never read
 constexpr unsigned kClassTiny = 1u;  // some image value with 0 < |I| < 2^-40
 constexpr unsigned kClassHuge = 2u;  // some image value with |I| > 2^60 or not finite
 

@@ -6,7 +6,9 @@
 
 namespace ggdt {
 
-constexpr int kToivThreads = 1024;  // threads per workgroup: one row (z, y) each per step
+constexpr int kToivThreads = 1024;  // threads per workgroup of the general form
+constexpr int kToivRowsImage = 256;   // rows per block of the ring form (one per thread): image bands
+constexpr int kToivRowsVolume = 512;  // volume slabs
 
 struct ToivDesc {
   const float* image;  // (C, N)
@@ -24,12 +26,16 @@ struct ToivDesc {
   // volume, or bands of `by` rows of an image (Z = 1, bz = 1); `nb` blocks.
   int bz, by, nb;
   int publish;  // steps between progress publications
+  int ng;       // ghost rows: the rows of the neighbouring block a block reads (H, image: 1)
+  int ring;     // 1: the LDS-ring form, 0: the general form
+  int threads;  // threads per workgroup
+  size_t lds;   // dynamic LDS bytes of the launch
 };
 
-// Pick the row blocks of a problem (at most `cap` of them, one workgroup each,
-// and at most `words` progress words); false if none fits.
-bool toivanen_blocks(ToivDesc* d, int cap, long long words);
-int toivanen_capacity();
+// Pick the form and row blocks of a problem (one workgroup each, all
+// co-resident, at most `words` progress words): GGDT_OK, GGDT_ERR_UNSUPPORTED
+// if none fits, GGDT_ERR_HIP if the device cannot be queried.
+int toivanen_plan(ToivDesc* d, long long words);
 hipError_t launch_toivanen(const ToivDesc& d, unsigned* words, unsigned long long spin_limit, hipStream_t stream);
 
 }  // namespace ggdt

@@ -76,9 +76,7 @@ int toivanen_entry(int ndim, const int* dims, int C, const float* image, const f
   if (rc) return rc;
   // progress words in the exchange area after the header
   const long long nwords = (long long)((workspace_for(pr, tu) - (size_t)kHeaderWords * 4) / 8);
-  const int cap = toivanen_capacity();
-  if (cap <= 0) return GGDT_ERR_HIP;
-  if (!toivanen_blocks(&d, cap, nwords)) return GGDT_ERR_UNSUPPORTED;
+  if ((rc = toivanen_plan(&d, nwords))) return rc;
   unsigned* words = (unsigned*)ws;
   if (launch_reset(words, (long long)(workspace_for(pr, tu) / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (launch_scale(mask, v, out, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;

@@ -2,7 +2,8 @@
 sequential FP32 sweeps, bit for bit: 2D and 3D, 1-3 channels, lambda 0, general
 and 1, soft and hard seeds, unit dimensions, iterations 0-3, one row block and
 pipelines of several (ragged) row blocks (bands of 1024 image rows, slabs of
-1024 / H volume planes), up to the 256^3 benchmark volume (one iteration)."""
+1024 / H volume planes), the LDS-ring form and the general one (more than 3
+channels, or a block's rings beyond the LDS), up to the 256^3 benchmark volume (one iteration)."""
 import numpy as np
 import pytest
 
@@ -19,6 +20,10 @@ CASES = [
     ((70, 75, 9), 3, 0.7, 1, True), ((33, 40, 12), 1, 0.3, 0, True),
     ((2100, 37), 2, 0.6, 2, True), ((1030, 5), 1, 1.0, 1, False),  # 3 and 2 bands of image rows
     ((3, 1500, 4), 1, 0.9, 2, False), ((300, 16, 3), 1, 0.5, 2, True),  # slabs of 1 plane; 5 ragged slabs
+    # the general form: 4 channels; rows of a volume beyond the LDS rings (1500 > 1024 rows above, and
+    # 2 channels of 700 rows)
+    ((70, 41), 4, 0.7, 2, True), ((5, 700, 3), 2, 0.6, 1, True),
+    ((4, 600, 3), 1, 0.8, 2, False), ((6, 300, 5), 3, 0.5, 1, True),  # slabs of one plane: 1024 and 512 threads
 ]
 
 
