@@ -217,7 +217,7 @@ struct RingBlock {
 };
 
 // One sweep (DIR +1 forward, -1 backward) of a block; false if a wait gave up.
-template <int NOFF, int C, int NT, int DIR>
+template <int NOFF, int C, int NT, int DIR, int MODE>
 __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k0, float* lds, int* s_ok,
                                            unsigned* words, unsigned long long limit, unsigned long long base) {
   constexpr int S = NOFF == 13 ? 8 : 4;
@@ -352,13 +352,19 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
       const int offI = ghost ? offD + S * G : (S * R) + slot * R + lcol;
       const float dv = lds[offD];
       const float d0 = cI[0] - lds[offI];
-      float g = d0 * d0;
+      float w;
+      if (MODE == kModeLam1C1) {
+        w = fabsf(d0);  // = sqrtf(fl(d0 * d0)) for the classified image (no tiny or huge values)
+      } else {
+        float g = d0 * d0;
 #pragma unroll
-      for (int c = 1; c < C; ++c) {
-        const float dc = cI[c] - lds[offI + c * cs];
-        g = fmaf(dc, dc, g);
+        for (int c = 1; c < C; ++c) {
+          const float dc = cI[c] - lds[offI + c * cs];
+          g = fmaf(dc, dc, g);
+        }
+        w = general_root<MODE>(fmaf(d.lam, g, d.A[k]));
       }
-      const float cand = dv + sqrtf(fmaf(d.lam, g, d.A[k]));
+      const float cand = dv + w;
       if (ok && cand < best) best = cand;
     }
     if (active) {
@@ -395,7 +401,21 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
   return true;
 }
 
-template <int NOFF, int C, int NT>
+// The sweeps of one edge-cost form.
+template <int NOFF, int C, int NT, int MODE>
+__device__ __forceinline__ void ring_iterations(const ToivDesc& d, const RingBlock& k0, float* lds, int* s_ok,
+                                                unsigned* words, unsigned long long limit) {
+  for (int it = 0; it < d.iterations; ++it) {
+    const unsigned long long base = (unsigned long long)(2 * it) * (unsigned long long)d.T;
+    if (!ring_sweep<NOFF, C, NT, 1, MODE>(d, k0, lds, s_ok, words, limit, base)) return;
+    if (!ring_sweep<NOFF, C, NT, -1, MODE>(d, k0, lds, s_ok, words, limit, base + (unsigned long long)d.T)) return;
+  }
+}
+
+// RMODE: the form the host requested (kModeLam1C1 or kModeGeneral); the image
+// classification decides on the device whether its fast form applies, as for
+// the passes.
+template <int NOFF, int C, int NT, int RMODE>
 __global__ __launch_bounds__(NT) void toivanen_ring_kernel(ToivDesc d, unsigned* words, unsigned long long limit) {
   extern __shared__ __align__(16) float lds[];
   __shared__ int s_ok[2];
@@ -418,11 +438,13 @@ __global__ __launch_bounds__(NT) void toivanen_ring_kernel(ToivDesc d, unsigned*
   k0.y = k0.y0 + (k0.has_row ? k0.r - rz * k0.nry : 0);
   k0.row0 = ((long long)k0.z * H + k0.y) * W;  // voxel index of x = 0
   k0.t0 = 4 * k0.z + 2 * k0.y;                 // its hyperplane
-  for (int it = 0; it < d.iterations; ++it) {
-    const unsigned long long base = (unsigned long long)(2 * it) * (unsigned long long)d.T;
-    if (!ring_sweep<NOFF, C, NT, 1>(d, k0, lds, s_ok, words, limit, base)) return;
-    if (!ring_sweep<NOFF, C, NT, -1>(d, k0, lds, s_ok, words, limit, base + (unsigned long long)d.T)) return;
-  }
+  const unsigned cls = ld_relaxed(words + kWordClass);
+  if (RMODE == kModeLam1C1 && cls == 0u)
+    ring_iterations<NOFF, C, NT, kModeLam1C1>(d, k0, lds, s_ok, words, limit);
+  else if (RMODE == kModeGeneral && general_n_ok(d.sqrt_normal, words + kWordClass))
+    ring_iterations<NOFF, C, NT, kModeGeneralN>(d, k0, lds, s_ok, words, limit);
+  else
+    ring_iterations<NOFF, C, NT, kModeGeneral>(d, k0, lds, s_ok, words, limit);
 }
 
 }  // namespace
@@ -430,19 +452,20 @@ __global__ __launch_bounds__(NT) void toivanen_ring_kernel(ToivDesc d, unsigned*
 namespace {
 
 template <int NOFF, int NT>
-const void* ring_fn_c(int C) {
-  if (C == 1) return (const void*)toivanen_ring_kernel<NOFF, 1, NT>;
-  if (C == 2) return (const void*)toivanen_ring_kernel<NOFF, 2, NT>;
-  if (C == 3) return (const void*)toivanen_ring_kernel<NOFF, 3, NT>;
+const void* ring_fn_c(int C, int mode) {
+  if (mode == kModeLam1C1) return C == 1 ? (const void*)toivanen_ring_kernel<NOFF, 1, NT, kModeLam1C1> : nullptr;
+  if (C == 1) return (const void*)toivanen_ring_kernel<NOFF, 1, NT, kModeGeneral>;
+  if (C == 2) return (const void*)toivanen_ring_kernel<NOFF, 2, NT, kModeGeneral>;
+  if (C == 3) return (const void*)toivanen_ring_kernel<NOFF, 3, NT, kModeGeneral>;
   return nullptr;
 }
 
 // The block sizes the plan picks: image bands of up to 256 rows; volume slabs
 // of up to 512 rows, or one plane of up to 1024.
-const void* ring_fn(int noff, int C, int nt) {
-  if (noff == 4 && nt == 256) return ring_fn_c<4, 256>(C);
-  if (noff == 13 && nt == 512) return ring_fn_c<13, 512>(C);
-  if (noff == 13 && nt == 1024) return ring_fn_c<13, 1024>(C);
+const void* ring_fn(int noff, int C, int nt, int mode) {
+  if (noff == 4 && nt == 256) return ring_fn_c<4, 256>(C, mode);
+  if (noff == 13 && nt == 512) return ring_fn_c<13, 512>(C, mode);
+  if (noff == 13 && nt == 1024) return ring_fn_c<13, 1024>(C, mode);
   return nullptr;
 }
 
@@ -502,7 +525,7 @@ int toivanen_plan(ToivDesc* d, long long words) {
     const int nt = image ? 256 : (rows <= 512 ? 512 : 1024);
     const long long nb = set_blocks(bz, by);
     d->threads = nt;
-    const void* fn = ring_fn(d->noff, d->C, nt);
+    const void* fn = ring_fn(d->noff, d->C, nt, d->mode);
     const size_t lds = ring_lds(*d);
     if (fn && rows <= 1024 && lds <= 160 * 1024 && nb <= words) {
       const int cap = capacity(fn, nt, lds);
@@ -532,7 +555,7 @@ int toivanen_plan(ToivDesc* d, long long words) {
 hipError_t launch_toivanen(const ToivDesc& d, unsigned* words, unsigned long long spin_limit, hipStream_t stream) {
   const int grid = d.nb;
   if (grid <= 0) return hipErrorInvalidConfiguration;
-  const void* fn = d.ring ? ring_fn(d.noff, d.C, d.threads) : general_fn(d.noff);
+  const void* fn = d.ring ? ring_fn(d.noff, d.C, d.threads, d.mode) : general_fn(d.noff);
   if (!fn) return hipErrorInvalidValue;
   void* args[] = {(void*)&d, (void*)&words, (void*)&spin_limit};
   return hipLaunchKernel(fn, dim3(grid), dim3(d.threads), args, d.lds, stream);

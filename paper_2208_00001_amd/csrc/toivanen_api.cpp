@@ -51,6 +51,13 @@ int make_desc(const Problem& pr, const float* image, const float* spacing, float
         ++n;
       }
   d->noff = n;
+  // the edge cost's forms, chosen as for the passes: w = |I(x) - I(y)| for
+  // lambda 1 and one channel, else the root, in its normal-range form when
+  // every argument fmaf(lambda, g, A_j) >= A_j is at least 2^-96
+  d->mode = (lam == 1.0f && pr.C == 1) ? kModeLam1C1 : kModeGeneral;
+  float amin = d->A[0];
+  for (int j = 1; j < n; ++j) amin = d->A[j] < amin ? d->A[j] : amin;
+  d->sqrt_normal = amin >= 0x1p-96f ? 1 : 0;
   return GGDT_OK;
 }
 
@@ -81,6 +88,8 @@ int toivanen_entry(int ndim, const int* dims, int C, const float* image, const f
   if (launch_reset(words, (long long)(workspace_for(pr, tu) / 4), stream) != hipSuccess) return GGDT_ERR_HIP;
   if (launch_scale(mask, v, out, pr.N, stream) != hipSuccess) return GGDT_ERR_HIP;
   if (iterations == 0) return GGDT_OK;
+  // image classification (tiny or huge values), which picks the edge cost's form on the device
+  if (launch_classify(image, (long long)pr.C * pr.N, words, stream) != hipSuccess) return GGDT_ERR_HIP;
   return launch_toivanen(d, words, g_spin_limit, stream) == hipSuccess ? GGDT_OK : GGDT_ERR_HIP;
 }
 

@@ -3,7 +3,8 @@ sequential FP32 sweeps, bit for bit: 2D and 3D, 1-3 channels, lambda 0, general
 and 1, soft and hard seeds, unit dimensions, iterations 0-3, one row block and
 pipelines of several (ragged) row blocks (bands of 1024 image rows, slabs of
 1024 / H volume planes), the LDS-ring form and the general one (more than 3
-channels, or a block's rings beyond the LDS), up to the 256^3 benchmark volume (one iteration)."""
+channels, or a block's rings beyond the LDS), the edge cost's fast forms and
+their fallbacks on extreme image values, up to the 256^3 benchmark volume (one iteration)."""
 import numpy as np
 import pytest
 
@@ -58,4 +59,36 @@ def test_toivanen_256_volume_one_iteration():
     ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], c["lam"], 1, "f32")
     got = to_host(B.ggdt_toivanen(to_dev(c["image"]), to_dev(c["mask"]), c["spacing"], c["v"], c["lam"], 1,
                                   check=True))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape,scale,lam", [((23, 31, 19), 1e-30, 1.0), ((23, 31, 19), 1e25, 1.0),
+                                             ((23, 31, 19), 1e25, 0.0), ((140, 90), 1e-30, 1.0),
+                                             ((140, 90), 1e25, 1.0)])
+def test_toivanen_fast_form_fallback_on_extreme_values(shape, scale, lam):
+    """lambda 1 with |I| < 2^-40, or |I| > 2^60, must take the root (the image
+    classification rules out w = |I(x) - I(y)|), as for the passes."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=1, seed=7, lam=lam, iterations=2)
+    c["image"] = (c["image"] * np.float32(scale)).astype(np.float32)
+    print(f"toivanen extreme {shape} scale={scale} lam={lam}", flush=True)
+    ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], lam, 2, "f32")
+    got = to_host(B.ggdt_toivanen(to_dev(c["image"]), to_dev(c["mask"]), c["spacing"], c["v"], lam, 2, check=True))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape,C,lam,spacing", [((29, 35, 26), 1, 0.3, (1.0, 0.5, 2.0)),
+                                                  ((21, 30, 17), 2, 0.9, (0.25, 1.0, 1.0)),
+                                                  ((260, 190), 1, 0.6, (3.0, 0.5))])
+def test_toivanen_general_root_over_wide_magnitudes(shape, C, lam, spacing):
+    """The general edge cost with image magnitudes log-uniform over [2^-40, 2^59]
+    (random signs), where a shortened correctly rounded root would go wrong."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=C, seed=11, lam=lam, iterations=2, spacing=spacing)
+    rng = np.random.default_rng(11)
+    e = rng.uniform(-40.0, 59.0, size=c["image"].shape)
+    c["image"] = (np.sign(rng.uniform(-1, 1, size=e.shape)) * np.exp2(e)).astype(np.float32)
+    print(f"toivanen wide {shape} C={C} lam={lam}", flush=True)
+    ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], 1e30, lam, 2, "f32")
+    got = to_host(B.ggdt_toivanen(to_dev(c["image"]), to_dev(c["mask"]), c["spacing"], 1e30, lam, 2, check=True))
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
