@@ -171,14 +171,19 @@ void edge_constants(const Problem& pr, int axis, const float* spacing, float lam
   }
 }
 
-// The general edge cost's root argument fmaf(lambda, g, A_j) is at least A_j, so
-// with every A_j >= 2^-96 (and finite image values, checked on the device) it
-// lies in the normal range that sqrt_rn_normal handles.
-int sqrt_normal_for(const float* A, int ndim) {
-  const int nj = ndim == 3 ? 9 : 3;
-  float amin = A[0];
-  for (int j = 1; j < nj; ++j) amin = A[j] < amin ? A[j] : amin;
-  return amin >= 0x1p-96f ? 1 : 0;
+// When the general edge cost's root argument fmaf(lambda, g, A_j) over the n
+// candidates' constants lies in the normal range that sqrt_rn_normal handles:
+// always when every A_j >= 2^-96 (it is at least A_j; finite image values are
+// checked on the device), and for lambda 1 (every A_j = 0, the argument is g)
+// when the device finds no small or huge image value.
+int sqrt_normal_for(const float* A, int n) {
+  float amin = A[0], amax = A[0];
+  for (int j = 1; j < n; ++j) {
+    amin = A[j] < amin ? A[j] : amin;
+    amax = A[j] > amax ? A[j] : amax;
+  }
+  if (amin >= 0x1p-96f) return kSqrtNormalUnlessHuge;
+  return amax == 0.0f ? kSqrtNormalLam1 : kSqrtNormalNever;
 }
 
 int requested_mode(float lam, int C) {
@@ -336,7 +341,7 @@ int build_pass(const Problem& pr, const float* image, const float* mask, const f
   d->init = p == 0 ? 1 : 0;
   d->rec = records ? records + (size_t)p * pr.N : nullptr;
   d->epoch_base = epoch_base;
-  d->sqrt_normal = sqrt_normal_for(d->A, pr.ndim);
+  d->sqrt_normal = sqrt_normal_for(d->A, pr.ndim == 3 ? 9 : 3);
   d->op = kOpPass;
   d->esz = 4;
   d->image_off = d->d_off = d->rec_off = -1;

@@ -335,7 +335,7 @@ __device__ __forceinline__ bool run_bwd_pass_cell_mode(const BwdDesc* gp, unsign
                                                        float* lds, int wg, int G) {
   const int mode = gp->mode;
   if (mode == kModeLam0) return run_bwd_pass_cell<kModeLam0>(gp, xbuf, words, limit, lds, wg, G);
-  if (mode == kModeLam1C1 && ld_relaxed(cls_word) == 0u)
+  if (mode == kModeLam1C1 && fast_mode_ok(kModeLam1C1, ld_relaxed(cls_word)))
     return run_bwd_pass_cell<kModeLam1C1>(gp, xbuf, words, limit, lds, wg, G);
   if (mode == kModeGeneral && general_n_ok(gp->sqrt_normal, cls_word))
     return run_bwd_pass_cell<kModeGeneralN>(gp, xbuf, words, limit, lds, wg, G);

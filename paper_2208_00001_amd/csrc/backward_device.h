@@ -411,7 +411,7 @@ __device__ __forceinline__ bool run_bwd_pass_mode(const BwdDesc* gp, unsigned lo
                                                   int wg, int G) {
   const int mode = gp->mode;
   if (mode == kModeLam0) return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam0, NT>(gp, xbuf, words, limit, lds, wg, G);
-  if (mode == kModeLam1C1 && ld_relaxed(cls_word) == 0u)
+  if (mode == kModeLam1C1 && fast_mode_ok(kModeLam1C1, ld_relaxed(cls_word)))
     return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeLam1C1, NT>(gp, xbuf, words, limit, lds, wg, G);
   if (mode == kModeGeneral && general_n_ok(gp->sqrt_normal, cls_word))
     return run_bwd_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN, NT>(gp, xbuf, words, limit, lds, wg, G);

@@ -113,14 +113,15 @@ __global__ __launch_bounds__(256) void batched_classify_kernel(const BatchInst* 
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < in.nimg; t += stride) {
       const float a = fabsf(to_gmem(in.image)[t]);
       if (!(a <= 0x1p60f)) bits |= kClassHuge;
-      else if (a != 0.0f && a < 0x1p-40f) bits |= kClassTiny;
+      else if (a != 0.0f && a < 0x1p-24f) bits |= a < 0x1p-40f ? (kClassSmall | kClassTiny) : kClassSmall;
     }
     const int tiny = __syncthreads_or((bits & kClassTiny) ? 1 : 0);
     const int huge = __syncthreads_or((bits & kClassHuge) ? 1 : 0);
-    if (threadIdx.x == 0 && (tiny || huge))
+    const int small = __syncthreads_or((bits & kClassSmall) ? 1 : 0);
+    if (threadIdx.x == 0 && (tiny || huge || small))
       __hip_atomic_fetch_or(reinterpret_cast<unsigned*>(ws + in.cls_off),
-                            (tiny ? kClassTiny : 0u) | (huge ? kClassHuge : 0u), __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
+                            (tiny ? kClassTiny : 0u) | (huge ? kClassHuge : 0u) | (small ? kClassSmall : 0u),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

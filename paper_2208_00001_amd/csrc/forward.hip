@@ -169,12 +169,14 @@ __global__ __launch_bounds__(256) void classify_kernel(const float* image, long 
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const float a = fabsf(widen<FMT>(img[i]));
     if (!(a <= 0x1p60f)) bits |= kClassHuge;
-    else if (a != 0.0f && a < 0x1p-40f) bits |= kClassTiny;
+    else if (a != 0.0f && a < 0x1p-24f) bits |= a < 0x1p-40f ? (kClassSmall | kClassTiny) : kClassSmall;
   }
   const int tiny = __syncthreads_or((bits & kClassTiny) ? 1 : 0);
   const int huge = __syncthreads_or((bits & kClassHuge) ? 1 : 0);
-  if (threadIdx.x == 0 && (tiny || huge))
-    __hip_atomic_fetch_or(words + kWordClass, (tiny ? kClassTiny : 0u) | (huge ? kClassHuge : 0u),
+  const int small = __syncthreads_or((bits & kClassSmall) ? 1 : 0);
+  if (threadIdx.x == 0 && (tiny || huge || small))
+    __hip_atomic_fetch_or(words + kWordClass,
+                          (tiny ? kClassTiny : 0u) | (huge ? kClassHuge : 0u) | (small ? kClassSmall : 0u),
                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -49,7 +49,7 @@ int check_alias(const void* out, size_t nout, const void* const* ins, const size
 void tile_shape(const Problem& pr, const Tuning& tu, int* TP, int* TQ);
 void pass_geometry(const Problem& pr, int axis, PassDesc* d);
 void edge_constants(const Problem& pr, int axis, const float* spacing, float lam, float* A, float* W0);
-int sqrt_normal_for(const float* A, int ndim);
+int sqrt_normal_for(const float* A, int n);  // kSqrtNormal* for the constants A_0..A_{n-1}
 int requested_mode(float lam, int C);
 int max_tiles(const Problem& pr, const Tuning& tu);
 int build_bwd_pass(const Problem& pr, const float* image, const uint8_t* records, const float* spacing, float lam,

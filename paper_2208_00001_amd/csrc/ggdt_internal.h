@@ -18,8 +18,15 @@ constexpr int kWordChanged = 2;
 constexpr int kWordDone = 3;
 constexpr int kWordIters = 4;
 constexpr int kWordSink = 5;    // written by idle lanes to keep a kernel's stores unconditional; never read
-constexpr unsigned kClassTiny = 1u;  // some image value with 0 < |I| < 2^-40
-constexpr unsigned kClassHuge = 2u;  // some image value with |I| > 2^60 or not finite
+constexpr unsigned kClassTiny = 1u;   // some image value with 0 < |I| < 2^-40
+constexpr unsigned kClassHuge = 2u;   // some image value with |I| > 2^60 or not finite
+constexpr unsigned kClassSmall = 4u;  // some image value with 0 < |I| < 2^-24 (implied by kClassTiny)
+// Values of PassDesc::sqrt_normal: when the general root's argument lies in
+// the normal range where kModeGeneralN's root gives sqrtf's bits.
+constexpr int kSqrtNormalNever = 0;
+constexpr int kSqrtNormalUnlessHuge = 1;  // min_j A_j >= 2^-96: fmaf(lambda, g, A_j) >= A_j
+constexpr int kSqrtNormalLam1 = 2;        // every A_j = 0 (lambda 1): the argument is g, which is 0 or in
+                                          // [2^-94, 2^126] when no image value is small or huge
 
 constexpr int kThreads = 256;         // threads per pass workgroup
 constexpr size_t kMaxLdsBytes = 159 * 1024;  // 160 KiB per CU, less room for static LDS
@@ -87,7 +94,7 @@ struct PassDesc {
   float A[9];          // (float)((1 - lambda) * |dx|_s^2) per offset j
   float W0[9];         // sqrtf(A[j]), used when lambda == 0
   unsigned epoch_base; // exchange words of chunk c carry epoch_base + c + 1
-  int sqrt_normal;     // min_j A[j] >= 2^-96: the general root may use kModeGeneralN
+  int sqrt_normal;     // kSqrtNormal*: when the general root may use kModeGeneralN
   int converge;        // convergence mode: skip when done, report changes in kWordChanged
   int img_fmt;         // ImgFmt of `image` (16-bit formats: image points to 2-byte elements)
   // Batched launches only.  op != kOpPass: instead of a pass, the instance's

@@ -514,8 +514,7 @@ __device__ __forceinline__ bool run_pass_cell_mode(const PassDesc* gp, unsigned 
       return run_pass_cell<SCANC, kModeGeneralN, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
     return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
   }
-  const unsigned cls = ld_relaxed(cls_word);
-  const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
+  const bool fast = fast_mode_ok(RMODE, ld_relaxed(cls_word));
   if (fast) return run_pass_cell<SCANC, RMODE, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
   return run_pass_cell<SCANC, kModeGeneral, REC, TT, KC, FMT>(gp, xbuf, words, limit, lds, wg, G);
 }

@@ -137,9 +137,23 @@ __device__ __forceinline__ PassDesc resolve_offsets(PassDesc g, unsigned* words)
 }
 
 // Mode for a pass whose requested mode RMODE is the general one: the
-// normal-range root when the spatial terms allow it and no image value is huge.
+// normal-range root when the spatial terms keep the argument at least 2^-96
+// and no image value is huge, or when they are all 0 (lambda 1: the argument
+// is g, a sum of squared channel differences) and no value is small or huge:
+// every non-zero difference is then at least 2^-47, so g is 0 (whose root
+// kModeGeneralN also gives exactly) or in [2^-94, 2^126].
 __device__ __forceinline__ bool general_n_ok(int sqrt_normal, const unsigned* cls_word) {
-  return sqrt_normal != 0 && (ld_relaxed(cls_word) & kClassHuge) == 0u;
+  const unsigned cls = ld_relaxed(cls_word);
+  if (sqrt_normal == kSqrtNormalUnlessHuge) return (cls & kClassHuge) == 0u;
+  if (sqrt_normal == kSqrtNormalLam1) return (cls & (kClassHuge | kClassSmall)) == 0u;
+  return false;
+}
+
+// The fast modes' condition on the classification: w = |I(x) - I(y)| (lambda 1,
+// one channel) needs no tiny and no huge value; w = sqrtf(A_j) (lambda 0) no
+// huge value.
+__device__ __forceinline__ bool fast_mode_ok(int mode, unsigned cls) {
+  return mode == kModeLam0 ? (cls & kClassHuge) == 0u : (cls & (kClassTiny | kClassHuge)) == 0u;
 }
 
 template <int MODE>
@@ -521,8 +535,7 @@ __device__ __forceinline__ bool run_pass_mode(const PassDesc* gp, unsigned long 
       return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneralN, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
     return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
   }
-  const unsigned cls = ld_relaxed(cls_word);
-  const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
+  const bool fast = fast_mode_ok(RMODE, ld_relaxed(cls_word));
   if (fast) return run_pass<NDIM, TP, TQ, K, SCANC, RMODE, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
   return run_pass<NDIM, TP, TQ, K, SCANC, kModeGeneral, REC, NT>(gp, xbuf, words, limit, lds, wg, G);
 }

@@ -284,8 +284,7 @@ __device__ __forceinline__ bool run_pass_row_mode(const PassDesc* gp, unsigned l
       return run_pass_row<kModeGeneralN, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
     return run_pass_row<kModeGeneral, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
   }
-  const unsigned cls = ld_relaxed(cls_word);
-  const bool fast = (RMODE == kModeLam0) ? (cls & kClassHuge) == 0u : cls == 0u;
+  const bool fast = fast_mode_ok(RMODE, ld_relaxed(cls_word));
   if (fast) return run_pass_row<RMODE, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
   return run_pass_row<kModeGeneral, NCH, REC, FMT>(gp, xbuf, words, limit, wg, G);
 }

@@ -1,5 +1,6 @@
 // Rounding correction of a square root: given x in [2^-96, FLT_MAX] and s, a
-// float within one ulp of sqrt(x), return the correctly rounded sqrtf(x).
+// float within one ulp of sqrt(x), return the correctly rounded sqrtf(x); for
+// x = +0 (with s = +0 or the next float) it returns +0.
 //
 // This is the Tuckerman rounding test, in the form Markstein gives for fused
 // multiply-add hardware: with lo and hi the floats next to s, the residuals

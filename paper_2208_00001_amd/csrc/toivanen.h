@@ -28,7 +28,7 @@ struct ToivDesc {
   int publish;  // steps between progress publications
   int ng;       // ghost rows: the rows of the neighbouring block a block reads (H, image: 1)
   int mode;         // kModeLam1C1 (lambda 1, one channel) or kModeGeneral, as the passes request
-  int sqrt_normal;  // every A_j >= 2^-96: the general root's argument lies in the normal range
+  int sqrt_normal;  // kSqrtNormal*: when the general root may take its normal-range form
   int ring;     // 1: the LDS-ring form, 0: the general form
   int threads;  // threads per workgroup
   size_t lds;   // dynamic LDS bytes of the launch

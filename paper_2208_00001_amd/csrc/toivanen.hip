@@ -439,7 +439,7 @@ __global__ __launch_bounds__(NT) void toivanen_ring_kernel(ToivDesc d, unsigned*
   k0.row0 = ((long long)k0.z * H + k0.y) * W;  // voxel index of x = 0
   k0.t0 = 4 * k0.z + 2 * k0.y;                 // its hyperplane
   const unsigned cls = ld_relaxed(words + kWordClass);
-  if (RMODE == kModeLam1C1 && cls == 0u)
+  if (RMODE == kModeLam1C1 && fast_mode_ok(kModeLam1C1, cls))
     ring_iterations<NOFF, C, NT, kModeLam1C1>(d, k0, lds, s_ok, words, limit);
   else if (RMODE == kModeGeneral && general_n_ok(d.sqrt_normal, words + kWordClass))
     ring_iterations<NOFF, C, NT, kModeGeneralN>(d, k0, lds, s_ok, words, limit);

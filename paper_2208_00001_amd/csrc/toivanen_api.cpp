@@ -52,12 +52,10 @@ int make_desc(const Problem& pr, const float* image, const float* spacing, float
       }
   d->noff = n;
   // the edge cost's forms, chosen as for the passes: w = |I(x) - I(y)| for
-  // lambda 1 and one channel, else the root, in its normal-range form when
-  // every argument fmaf(lambda, g, A_j) >= A_j is at least 2^-96
+  // lambda 1 and one channel, else the root, in its normal-range form where
+  // the argument is known to allow it
   d->mode = (lam == 1.0f && pr.C == 1) ? kModeLam1C1 : kModeGeneral;
-  float amin = d->A[0];
-  for (int j = 1; j < n; ++j) amin = d->A[j] < amin ? d->A[j] : amin;
-  d->sqrt_normal = amin >= 0x1p-96f ? 1 : 0;
+  d->sqrt_normal = sqrt_normal_for(d->A, n);
   return GGDT_OK;
 }
 

@@ -2,7 +2,7 @@
 // (sqrt_round_fix in the library's sqrt_fix.h, included verbatim): for every
 // float x in [2^-96, FLT_MAX] and every s one float below, at, and one float
 // above the correctly rounded root r = sqrtf(x) (the host's IEEE square root),
-// sqrt_round_fix(x, s) must return r.  A hardware root within one ulp of the
+// sqrt_round_fix(x, s) must return r; and for x = +0 it must return +0.  A hardware root within one ulp of the
 // exact root is always one of these three floats, so this proves the kernels'
 // fast root equal to sqrtf over that range, whatever the hardware's exact error.
 //
@@ -52,7 +52,17 @@ int main() {
       }
     }
   }
-  printf("checked %lld (x, s) pairs over [2^-96, FLT_MAX]; failures %lld\n", checked, bad);
+  // x = +0 (lambda 1 where all channels of two pixels are equal): the root is
+  // +0, for s = +0 and for s one float above it
+  for (uint32_t sb = 0; sb <= 1; ++sb) {
+    ++checked;
+    if (to_bits(sqrt_round_fix(0.0f, from_bits(sb))) != 0u) {
+      ++bad;
+      bad_x = 0u;
+      bad_k = (int)sb;
+    }
+  }
+  printf("checked %lld (x, s) pairs over [2^-96, FLT_MAX] and x = +0; failures %lld\n", checked, bad);
   if (bad) printf("e.g. x = %a (bits 0x%08x), s = r %+d ulp\n", from_bits(bad_x), bad_x, bad_k);
   return bad ? 1 : 0;
 }

@@ -157,3 +157,21 @@ def test_config5_batched_forward_backward():
         assert torch.equal(out, d["out"]) and torch.equal(rec, d["records"]), f"volume {k} forward"
         assert torch.equal(gi, grads[k][0]) and torch.equal(gm, grads[k][1]), f"volume {k} backward"
     plan.close()
+
+
+@pytest.mark.parametrize("shape,C,scale", [((21, 26, 19), 2, 1.0), ((140, 90), 3, 1.0), ((18, 22, 20), 2, 2.0 ** -30)],
+                         ids=lambda v: str(v))
+def test_backward_lam1_multichannel_root_forms(shape, C, scale):
+    """The reverse pass at lambda 1 with several channels and a quantised image
+    (equal neighbours: a zero root argument), in the normal-range root's domain
+    and, with values near 2^-30, outside it."""
+    c = synth.small_case(shape, C=C, seed=720 + C, lam=1.0, iterations=2, soft=True, v=10.0)
+    c["image"] = (np.round(c["image"] * 2.0) * np.float32(scale)).astype(np.float32)
+    W = np.random.default_rng(721).standard_normal(shape).astype(np.float32)
+    print(f"case {c['name']} C={C} scale={scale}", flush=True)
+    out, rec, gi, gm = gpu_fwd_bwd(c, W)
+    ref, ref_rec = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], 1.0, 2, "f32", records=True)
+    assert np.array_equal(out, ref) and np.array_equal(rec, ref_rec)
+    rgi, rgm = oracle.backward(c["image"], ref_rec, W, c["spacing"], c["v"], 1.0, 2, "f32")
+    assert assert_parity(gm, rgm, what="dL/dM"), "dL/dM not bitwise"
+    assert assert_parity(gi.reshape(rgi.shape), rgi, what="dL/dI"), "dL/dI not bitwise"

@@ -150,3 +150,24 @@ def test_small_ragged_batch_backward(kind):
         assert assert_parity(to_host(grads[k][1]), rgm, what="dL/dM"), c["name"]
         assert assert_parity(to_host(grads[k][0]).reshape(rgi.shape), rgi, what="dL/dI"), c["name"]
     plan.close()
+
+
+def test_batch_lam1_multichannel_root_forms():
+    """lambda 1 with several channels in one batch: each instance's own image
+    classification picks the normal-range root (quantised images, zero root
+    arguments) or the full root (values near 2^-30)."""
+    from paper_2208_00001_amd.batched import BatchedPlan
+    cases = []
+    for k, (shape, C, scale) in enumerate([((80, 70), 3, 1.0), ((17, 21, 19), 2, 1.0), ((16, 20, 18), 2, 2.0 ** -30),
+                                           ((90, 60), 2, 2.0 ** -30)]):
+        c = synth.small_case(shape, C=C, seed=330 + k, lam=1.0, iterations=2)
+        c["image"] = (np.round(c["image"] * 2.0) * np.float32(scale)).astype(np.float32)
+        cases.append(c)
+    plan = BatchedPlan(to_instances(cases))
+    plan.run()
+    assert plan.status() == 0
+    for c, d in zip(cases, plan.inst):
+        print(f"instance {c['name']} C={c['image'].shape[0]}", flush=True)
+        ref = oracle.ggdt(c["image"], c["mask"], c["spacing"], c["v"], 1.0, 2, "f32")
+        assert np.array_equal(to_host(d["out"]).view(np.uint32), ref.view(np.uint32)), c["name"]
+    plan.close()

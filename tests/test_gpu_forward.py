@@ -168,3 +168,19 @@ def test_scan_major_and_in_place_last_axis(shape, lam, it):
         got = to_host(B.ggdt3d(img, m, c["spacing"], c["v"], c["lam"], c["iterations"], workspace=ws))
         assert B.workspace_status(ws) == 0, "watchdog fired"
         assert assert_parity(got, ref, what=f"{shape} minimal={minimal}"), "not bitwise"
+
+
+@pytest.mark.parametrize("shape,C,quantised,scale", [((70, 90), 3, True, 1.0), ((20, 24, 18), 2, True, 1.0),
+                                                     ((64, 65), 2, False, 2.0 ** -30),
+                                                     ((19, 23, 17), 3, True, 2.0 ** -30)])
+def test_lam1_multichannel_root_forms(shape, C, quantised, scale):
+    """lambda 1 with several channels: every A_j is 0, so the root's argument is
+    the sum of squared channel differences.  With no image value below 2^-24 the
+    normal-range root applies (and gives 0 for equal pixels, frequent in a
+    quantised image); with small values (2^-30 here) the full root must run."""
+    c = synth.small_case(shape, C=C, seed=19, lam=1.0, iterations=2)
+    img = c["image"]
+    if quantised:
+        img = np.round(img * 2.0).astype(np.float32)  # a few levels: many equal neighbours
+    c["image"] = (img * np.float32(scale)).astype(np.float32)
+    check_case(c)

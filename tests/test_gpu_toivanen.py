@@ -92,3 +92,16 @@ def test_toivanen_general_root_over_wide_magnitudes(shape, C, lam, spacing):
     ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], 1e30, lam, 2, "f32")
     got = to_host(B.ggdt_toivanen(to_dev(c["image"]), to_dev(c["mask"]), c["spacing"], 1e30, lam, 2, check=True))
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape,C,scale", [((60, 70), 3, 1.0), ((14, 18, 16), 2, 1.0), ((14, 18, 16), 2, 2.0 ** -30)])
+def test_toivanen_lam1_multichannel_root_forms(shape, C, scale):
+    """lambda 1, several channels, a quantised image (zero root arguments): the
+    normal-range root, and the full root for values near 2^-30."""
+    from paper_2208_00001_amd import binding as B
+    c = synth.small_case(shape, C=C, seed=23, lam=1.0, iterations=2)
+    c["image"] = (np.round(c["image"] * 2.0) * np.float32(scale)).astype(np.float32)
+    print(f"toivanen lam1 {shape} C={C} scale={scale}", flush=True)
+    ref = oracle.toivanen(c["image"], c["mask"], c["spacing"], c["v"], 1.0, 2, "f32")
+    got = to_host(B.ggdt_toivanen(to_dev(c["image"]), to_dev(c["mask"]), c["spacing"], c["v"], 1.0, 2, check=True))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
