@@ -225,11 +225,20 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
   // offsets 0..KG-1 leave the block through its boundary face (dz != 0 in a
   // volume slab, dy != 0 in an image band); the others stay inside
   constexpr int KG = NOFF == 13 ? 9 : 3;
-  const int G = d.ng;
-  float* rD = lds;             // [S][R]    D of the block's rows
-  float* rI = rD + S * R;      // [C][S][R] their image values
-  float* gD = rI + C * S * R;  // [S][G]    D of the ghost rows
-  float* gI = gD + S * G;      // [C][S][G]
+  // Ring rows of R1 = R + 1 (ghost: G1 = G + 1) columns: column r holds row r
+  // of the block, the last column +inf, read in place of a neighbour outside
+  // the domain.  A row idle at a step writes +inf into its slot, the rings
+  // start every sweep at +inf, and the ghost loader writes +inf where the
+  // ghost voxel does not exist: a missing neighbour's candidate is then +inf
+  // (or NaN) and never passes the strict <, as if it were skipped.
+  constexpr int R1 = R + 1;
+  const int G = d.ng, G1 = G + 1;
+  const float inf = __builtin_inff();
+  float* rD = lds;               // [S][R1]    D of the block's rows
+  float* rI = rD + S * R1;       // [C][S][R1] their image values
+  float* gD = rI + C * S * R1;   // [S][G1]    D of the ghost rows
+  float* gI = gD + S * G1;       // [C][S][G1]
+  const int gbase = (1 + C) * S * R1;  // gD's offset in the LDS
   const gmem<const float> I = to_gmem(d.image);
   const gmem<float> D = to_gmem(d.D);
   const gmem<float> sink = to_gmem(reinterpret_cast<float*>(words + kWordSink));
@@ -253,16 +262,30 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
   const int gcol = image ? 0 : r;
   const long long grow0 = ((long long)zg * H + yg) * W;
   const int tg0 = 4 * zg + 2 * yg;
-  // this row's neighbour rows: inside the domain per offset component, and
-  // whether the boundary-face offsets reach the ghost rows
-  const bool zlo = z - 1 >= 0, zhi = z + 1 < Z, ylo = y - 1 >= 0, yhi = y + 1 < H;
+  // whether this row's boundary-face offsets reach the ghost rows, and each
+  // candidate's column (ring offset at slot 0) and ring stride
   const bool edge = image ? (y == (DIR > 0 ? k0.y0 : k0.y1 - 1)) : (z == (DIR > 0 ? k0.z0 : k0.z1 - 1));
+  const int estride = edge ? G1 : R1;  // stride of the offsets 0..KG-1
+  int col[NOFF];
+#pragma unroll
+  for (int k = 0; k < NOFF; ++k) {
+    const int dz = DIR * ring_off<NOFF>(k, 0), dy = DIR * ring_off<NOFF>(k, 1);
+    const int zz = z + dz, yy = y + dy;
+    const bool there = has_row && zz >= 0 && zz < Z && yy >= 0 && yy < H;
+    if (k < KG && edge)
+      col[k] = gbase + (there ? (image ? 0 : yy) : G);
+    else
+      col[k] = there ? r + dz * k0.nry + dy : R;
+  }
   unsigned long long known = 0;
   // the neighbour's steps up to u_lo + 1: the ghosts of the first step and the first ghost load
   if (r == 0) {
     const unsigned long long need = base + (unsigned long long)(u_lo + 2);
     s_ok[0] = !has_dep || wait_progress(prog, dep, need < end ? need : end, known, words, limit);
   }
+  // the rings' D at +inf (the last columns stay so)
+  for (int i = r; i < S * R1; i += NT) rD[i] = inf;
+  for (int i = r; i < S * G1; i += NT) gD[i] = inf;
   __syncthreads();
   if (!s_ok[0]) return false;
   float pD = 0.0f, pI[C];  // the loader's ghost voxel of the current step
@@ -286,9 +309,9 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
         px = xg;
       } else {
         const int slot = ug & (S - 1);
-        gD[slot * G + gcol] = vD;
+        gD[slot * G1 + gcol] = vD;
 #pragma unroll
-        for (int c = 0; c < C; ++c) gI[(c * S + slot) * G + gcol] = vI[c];
+        for (int c = 0; c < C; ++c) gI[(c * S + slot) * G1 + gcol] = vI[c];
       }
     }
   }
@@ -311,12 +334,13 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
   for (int u = u_lo; u <= u_hi; ++u) {
     const int t = DIR > 0 ? u : T - 1 - u;
     const bool more = u < u_hi;
-    // the ghost voxel of this step into its slot (loaded a step ago)
-    if (px >= 0) {
+    // the ghost voxel of this step into its slot (loaded a step ago), +inf
+    // where there is none
+    if (loader) {
       const int slot = u & (S - 1);
-      gD[slot * G + gcol] = pD;
+      gD[slot * G1 + gcol] = px >= 0 ? pD : inf;
 #pragma unroll
-      for (int c = 0; c < C; ++c) gI[(c * S + slot) * G + gcol] = pI[c];
+      for (int c = 0; c < C; ++c) gI[(c * S + slot) * G1 + gcol] = pI[c];
     }
     // the next step's loads, issued by every thread at a clamped index
     // (their values unused where the voxel does not exist), so that no wait
@@ -333,23 +357,16 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
     }
     const int x = t - t0;
     const bool active = has_row && x >= 0 && x < W;
-    const bool xlo = x - 1 >= 0, xhi = x + 1 < W;
     float best = cD;
 #pragma unroll
     for (int k = 0; k < NOFF; ++k) {
-      const int dz = DIR * ring_off<NOFF>(k, 0), dy = DIR * ring_off<NOFF>(k, 1), dx = DIR * ring_off<NOFF>(k, 2);
       // steps back to the neighbour's hyperplane, and its ring slot (uniform)
       const int a = -(4 * ring_off<NOFF>(k, 0) + 2 * ring_off<NOFF>(k, 1) + ring_off<NOFF>(k, 2));
       const int slot = (u - a) & (S - 1);
-      const bool ok = (dz < 0 ? zlo : dz > 0 ? zhi : true) && (dy < 0 ? ylo : dy > 0 ? yhi : true) &&
-                      (dx < 0 ? xlo : dx > 0 ? xhi : true);
-      const bool ghost = k < KG && edge;
-      // the neighbour's column in its ring (the row itself where the neighbour does not exist)
-      const int lcol = ok ? r + dz * k0.nry + dy : r;
-      const int gc = image ? 0 : (ok ? y + dy : 0);
-      const int offD = ghost ? (S * R * (1 + C)) + slot * G + gc : slot * R + lcol;
-      const int cs = ghost ? S * G : S * R;  // channel stride
-      const int offI = ghost ? offD + S * G : (S * R) + slot * R + lcol;
+      const int stride = k < KG ? estride : R1;
+      const int cs = S * stride;  // from D to the image values, and between channels
+      const int offD = col[k] + slot * stride;
+      const int offI = offD + cs;
       const float dv = lds[offD];
       const float d0 = cI[0] - lds[offI];
       float w;
@@ -365,13 +382,13 @@ __device__ __forceinline__ bool ring_sweep(const ToivDesc& d, const RingBlock& k
         w = general_root<MODE>(fmaf(d.lam, g, d.A[k]));
       }
       const float cand = dv + w;
-      if (ok && cand < best) best = cand;
+      if (cand < best) best = cand;
     }
-    if (active) {
+    {
       const int slot = u & (S - 1);
-      rD[slot * R + r] = best;
+      rD[slot * R1 + r] = active ? best : inf;
 #pragma unroll
-      for (int c = 0; c < C; ++c) rI[(c * S + slot) * R + r] = cI[c];
+      for (int c = 0; c < C; ++c) rI[(c * S + slot) * R1 + r] = cI[c];
     }
     // the result, stored by every thread (idle ones to the sink word)
     *(active ? &D[row0 + x] : sink) = best;
@@ -489,7 +506,7 @@ int capacity(const void* fn, int threads, size_t lds) {
 // the block's rows (one per thread) and its ghost rows.
 size_t ring_lds(const ToivDesc& d) {
   const size_t S = d.noff == 13 ? 8 : 4;
-  return (size_t)(1 + d.C) * S * (size_t)(d.threads + d.ng) * sizeof(float);
+  return (size_t)(1 + d.C) * S * (size_t)(d.threads + 1 + d.ng + 1) * sizeof(float);
 }
 
 }  // namespace
